@@ -1,0 +1,100 @@
+"""Pins for the oracle's balance statistic M (CPU only)."""
+
+from math import comb
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import assign, balance, prep
+
+
+def all_M(X, n1, ridge_rel=0.0):
+    P = prep.prepare(X, n1, ridge_rel)
+    W = assign.exact_assignments(X.shape[0], n1)
+    return W, balance.mahalanobis_batch(X, W, P["S_lam"]), P
+
+
+def test_mean_over_all_assignments_is_d():
+    # E_w[M] = (n1 n0 / n) tr(S^-1 Cov_w(Delta)) and Cov_w(Delta) = n/(n1 n0) S exactly
+    # under complete randomization, so the mean over all C(n, n1) assignments is d.
+    X = np.random.default_rng(0).standard_normal((12, 3))
+    _, M, _ = all_M(X, 6)
+    assert abs(M.mean() - 3.0) < 1e-12
+
+
+def test_mean_with_ridge_is_trace():
+    X = np.random.default_rng(1).standard_normal((11, 4))
+    _, M, P = all_M(X, 4, ridge_rel=0.3)
+    want = np.trace(np.linalg.solve(P["S_lam"], P["S"]))
+    assert abs(M.mean() - want) < 1e-12
+    assert want < 4.0
+
+
+def test_range_and_complement_symmetry():
+    X = np.random.default_rng(2).standard_normal((12, 5))
+    W, M, P = all_M(X, 6)
+    assert M.min() >= 0 and M.max() <= 12 - 1 + 1e-9
+    Mc = balance.mahalanobis_batch(X, 1 - W, P["S_lam"])
+    np.testing.assert_allclose(Mc, M, rtol=1e-12, atol=1e-12)
+
+
+def test_affine_invariance():
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((30, 4))
+    A = rng.standard_normal((4, 4)) + 3 * np.eye(4)
+    b = rng.standard_normal(4) * 10
+    W = assign.mc_assignments_batch(5, np.arange(50, dtype=np.uint64), 30, 13)
+    M1 = balance.mahalanobis_batch(X, W, prep.prepare(X, 13)["S_lam"])
+    Y = X @ A + b
+    M2 = balance.mahalanobis_batch(Y, W, prep.prepare(Y, 13)["S_lam"])
+    np.testing.assert_allclose(M1, M2, rtol=1e-9)
+
+
+def test_whitened_sum_form_agrees():
+    # M = n/(n1 n0) || L^-1 sum_{i in T} (X_i - mu) ||^2, the whitened form of the
+    # Appendix A remark, with the centring that makes the control sum redundant.
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((40, 6))
+    P = prep.prepare(X, 17, ridge_rel=0.05)
+    W = assign.mc_assignments_batch(11, np.arange(30, dtype=np.uint64), 40, 17)
+    G = W @ (X - P["mu"])
+    Z = np.linalg.solve(P["L"], G.T).T
+    alt = 40 / (17 * 23) * (Z ** 2).sum(axis=1)
+    np.testing.assert_allclose(balance.mahalanobis_batch(X, W, P["S_lam"]), alt, rtol=1e-12)
+
+
+def test_chi2_scale():
+    # Section 2.2: M ~ (1/n_T + 1/n_C) chi^2_d on the paper's scale for whitened Gaussian
+    # covariates, i.e. chi^2_d on the scale reported here.
+    n, d, N = 2000, 10, 3000
+    X = np.random.default_rng(5).standard_normal((n, d))
+    P = prep.prepare(X, n // 2)
+    W = assign.mc_assignments_batch(17, np.arange(N, dtype=np.uint64), n, n // 2)
+    M = balance.mahalanobis_batch(X, W, P["S_lam"])
+    assert stats.kstest(M, stats.chi2(d).cdf).pvalue > 1e-3
+    assert abs(M.mean() - d) < 4 * np.sqrt(2 * d / N)
+
+
+def test_singular_detected():
+    X = np.random.default_rng(6).standard_normal((10, 12))
+    with pytest.raises(prep.SingularCovariance):
+        prep.prepare(X, 5, 0.0)
+    P = prep.prepare(X, 5, 1e-2)          # ridge makes it positive definite
+    assert np.all(np.diag(P["L"]) > 0)
+
+
+def test_rank_deficient_pinv_is_constant():
+    # Without a ridge and with d >= n - 1, the pseudo-inverse makes M = n - 1 for every
+    # draw (why a ridge is needed for the n = d workloads).
+    n = 15
+    X = np.random.default_rng(7).standard_normal((n, n))
+    mu, S = prep.covariance(X)
+    W = assign.mc_assignments_batch(3, np.arange(20, dtype=np.uint64), n, 7)
+    d = W @ X / 7 - (1 - W) @ X / 8
+    M = 7 * 8 / n * np.einsum("bj,jk,bk->b", d, np.linalg.pinv(S), d)
+    np.testing.assert_allclose(M, n - 1, rtol=1e-8)
+
+
+def test_exact_enumeration_count():
+    assert comb(20, 10) == 184756
