@@ -1,0 +1,197 @@
+/*
+ * rr.h -- C ABI of the MI355X (gfx950) rerandomization library, librr.so.
+ *
+ * The library implements the data-parallel hot path of rerandomization with key-only
+ * storage as described in Goldstein, Jerzak, Kamat & Zhu, "FastRerandomize: Fast
+ * Rerandomization Using Accelerated Computing":
+ *   - whitening of the covariates (section 2.2; Appendix A remark on general Sigma_X),
+ *   - batched candidate generation, balance evaluation and acceptance, keeping only the
+ *     keys of accepted draws (section 2.1 "Batched processing", "Key-only storage";
+ *     section 2.3 generate_randomizations),
+ *   - the randomization test conditioned on acceptance over a grid of sharp nulls
+ *     (section 2.3 randomization_test; section 4 "Design-based inference").
+ *
+ * Conventions shared by every call
+ *   - Pointers named d_* are device pointers (HBM of the current HIP device); pointers
+ *     named h_* are host pointers.  The caller owns all of them.
+ *   - `stream` is a hipStream_t passed as void* (0 = the null stream).  Calls enqueue their
+ *     kernels on it and return after the work has completed (they synchronise the stream
+ *     when a data-dependent size must be known on the host), so outputs are ready on return.
+ *   - On any error nothing is written to the outputs, except RR_E_CAPACITY, which writes
+ *     the required count to *h_count.  rr_last_error() returns a message for the last
+ *     failing call of the calling thread.
+ *   - A handle (rr_problem) owns its device workspace; it is not thread-safe: use one
+ *     handle per host thread / stream.
+ *
+ * The balance statistic is reported on the chi^2_d scale,
+ *     M(w) = (n1 n0 / n) (xbar_T - xbar_C)^T S_lam^-1 (xbar_T - xbar_C),
+ * i.e. the paper's M = Delta^T Sigma_X^-1 Delta (section 2.2) divided by (1/n1 + 1/n0).
+ */
+#ifndef RR_H
+#define RR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rr_problem rr_problem;
+
+typedef enum {
+    RR_OK = 0,
+    RR_E_ARG = 1,        /* invalid argument (sizes, null pointers, q outside (0,1], ...) */
+    RR_E_SINGULAR = 2,   /* covariance not positive definite after the ridge */
+    RR_E_CAPACITY = 3,   /* output capacity too small; *h_count holds the required count */
+    RR_E_RANGE = 4,      /* value outside the exactly representable range (see call) */
+    RR_E_OBS = 5,        /* observed-assignment index not among the accepted keys */
+    RR_E_DEVICE = 6,     /* HIP runtime error (message in rr_last_error) */
+    RR_E_UNSUPPORTED = 7 /* shape beyond this build's limits (see call) */
+} rr_status;
+
+enum { RR_MODE_QUANTILE = 0, RR_MODE_THRESHOLD = 1 };
+enum { RR_PREC_SPLIT_BF16 = 0, RR_PREC_FP32 = 1 };
+enum { RR_X_FP64 = 0, RR_X_FP32 = 1 };
+
+/* Largest unit count of a Monte Carlo problem in this build. */
+#define RR_MAX_N 4096
+/* Largest unit count for exact enumeration (bitmask of one 64-bit word). */
+#define RR_MAX_N_EXACT 64
+
+/*
+ * rr_prepare -- whitening and workspace set-up (section 2.2: covariates whitened so that
+ * Sigma_X = I; Appendix A remark: X~ = X Sigma^-1/2 gives M = ||Delta~||^2).
+ *
+ *   d_X      device, n rows x d columns, row-major with leading dimension ldx >= d,
+ *            FP64 (x_dtype = RR_X_FP64) or FP32 (RR_X_FP32, promoted to FP64).
+ *   n1       treated-group size, 1 <= n1 <= n-1.  n <= RR_MAX_N, d >= 1.
+ *   ridge_rel  lambda = ridge_rel * tr(S) / d is added to the diagonal of the sample
+ *            covariance S (denominator n - 1) before the Cholesky factorisation; >= 0.
+ *            With d >= n - 1, S is singular and ridge_rel > 0 is required.
+ *   out      receives the handle.
+ * Computes on the device, in FP64: column means mu, S, S_lam = S + lambda I, its
+ * Cholesky factor L, the whitened centred covariates X~ = (X - 1 mu^T) L^-T, and from X~
+ * the BF16 hi/lo and FP32 operand copies used by rr_draw_*.
+ * Errors: RR_E_ARG, RR_E_SINGULAR (a pivot <= 0, or min L_jj^2 < 1e-10 max S_jj),
+ * RR_E_UNSUPPORTED (n > RR_MAX_N), RR_E_DEVICE.
+ */
+rr_status rr_prepare(const void* d_X, int x_dtype, int64_t n, int64_t d, int64_t ldx,
+                     int64_t n1, double ridge_rel, void* stream, rr_problem** out);
+
+/* Releases a handle and its device memory.  Null is ignored. */
+void rr_free(rr_problem* p);
+
+/* Message of the last error of the calling thread ("" if none). */
+const char* rr_last_error(void);
+
+/* Read-only views of a prepared problem (host values). */
+int64_t rr_problem_n(const rr_problem* p);
+int64_t rr_problem_d(const rr_problem* p);
+int64_t rr_problem_n1(const rr_problem* p);
+double rr_problem_lambda(const rr_problem* p);
+
+/*
+ * rr_draw_balance -- Monte Carlo pool generation with key-only storage (section 2.3
+ * generate_randomizations with randomization_type = "monte_carlo"; section 2.1).
+ *
+ * Draw keys are the integers b in [key_begin, key_begin + num_draws).  Draw b treats the
+ * n1 units with the smallest (u_i, i), where u_i is word (i/64) mod 4 of Philox-4x32-10
+ * block 64*(i/256) + i%64 under counter (block, 0, lo32(b), hi32(b)) and key
+ * (lo32(seed), hi32(seed)).  M is computed for every draw; the accepted draws are
+ *   mode = RR_MODE_THRESHOLD: those with M <= q_or_a (section 2.2, Appendix A part C);
+ *   mode = RR_MODE_QUANTILE:  k = ceil(q N (1 - 1e-12)) draws with the smallest M
+ *     (section 2.2, acceptance probability q), q = q_or_a in (0, 1]; values within a
+ *     relative 1e-10 of the k-th smallest are ordered by key.
+ * precision selects the operand format of the W X~ contraction: RR_PREC_SPLIT_BF16
+ * (X~ = hi + lo in BF16, FP32 accumulation) or RR_PREC_FP32.  Either way every draw whose
+ * FP32 value is not provably on one side of the acceptance boundary is recomputed in
+ * FP64, so the accepted set does not depend on the precision.
+ *
+ * Outputs (device, caller-allocated, `capacity` entries):
+ *   d_keys   accepted keys, ascending;
+ *   d_M      their M (the FP64 value when it was recomputed, else the FP32 value);
+ *   d_flags  optional (may be null): 1 where d_M holds the FP64 recomputation.
+ *   h_count  host: number of accepted draws.
+ * Errors: RR_E_ARG, RR_E_CAPACITY, RR_E_DEVICE.
+ */
+rr_status rr_draw_balance(rr_problem* p, uint64_t seed, uint64_t key_begin,
+                          uint64_t num_draws, int mode, double q_or_a, int precision,
+                          uint64_t* d_keys, double* d_M, uint8_t* d_flags,
+                          uint64_t capacity, uint64_t* h_count, void* stream);
+
+/*
+ * rr_draw_exact -- exact enumeration (section 2.3, randomization_type = "exact"): every
+ * assignment is drawn once; its key is its colex rank r = sum_t C(i_t, t) over the treated
+ * indices i_1 < ... < i_n1, r in [0, C(n, n1)).  Acceptance and outputs as in
+ * rr_draw_balance.  Requires n <= RR_MAX_N_EXACT and C(n, n1) < 2^40 (RR_E_RANGE).
+ */
+rr_status rr_draw_exact(rr_problem* p, int mode, double q_or_a, int precision,
+                        uint64_t* d_keys, double* d_M, uint8_t* d_flags,
+                        uint64_t capacity, uint64_t* h_count, void* stream);
+
+/*
+ * rr_regenerate -- assignments from keys (section 2.1 "Key-only storage": the PRNG
+ * regenerates an accepted assignment from its key on demand).
+ *   d_keys     device, K keys (draw indices, or colex ranks when exact != 0);
+ *   d_bits     device, K x ceil(n/32) uint32: bit (i % 32) of word i/32 of row k is 1 iff
+ *              unit i is treated in draw k.
+ */
+rr_status rr_regenerate(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys,
+                        uint64_t K, uint32_t* d_bits, void* stream);
+
+/*
+ * rr_balance_keys -- M of given draws by both device paths, for verification.
+ *   d_M32, d_err  device, K floats each (may be null): the FP32 value of the W X~
+ *                 contraction in the given precision and its rigorous error bound, so
+ *                 |M32 - M| <= err;
+ *   d_M64         device, K doubles (may be null): the FP64 recomputation.
+ */
+rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys,
+                          uint64_t K, int precision, float* d_M32, float* d_err,
+                          double* d_M64, void* stream);
+
+/*
+ * rr_rand_test -- randomization test conditioned on acceptance (section 2.3
+ * randomization_test; section 4 "Design-based inference").
+ *
+ *   d_keys, K    the accepted keys (device); the observed assignment is key d_keys[obs_index].
+ *   d_Y          device, n observed outcomes (FP64).
+ *   h_tau0, G    host, G sharp-null effects tau0 (H0: Y_i(1) - Y_i(0) = tau0 for all i).
+ *   d_counts     device, G uint64: c_g = #{k : |T_k(tau0_g)| >= |T_obs(tau0_g)|}, where
+ *                T_k(tau0) is the difference in means of Y - tau0 * w_obs under draw k;
+ *                the p-value is c_g / K (>= 1/K since w_obs is among the draws).
+ *   h_tau_hat    host (may be null): observed difference in means.
+ * The statistic is evaluated exactly on Y rounded to the grid 2^-s, s = 61 - t - e with
+ * n^2 <= 2^t and max|Y| = f 2^e, f in [0.5, 1).  RR_E_RANGE if a tau0 is too large or too
+ * finely resolved for the 128-bit comparison (|tau0| >= 2^-8 and |tau0| < 2^20 are
+ * always accepted, as is tau0 = 0); RR_E_OBS if obs_index >= K.
+ */
+rr_status rr_rand_test(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys,
+                       uint64_t K, uint64_t obs_index, const double* d_Y,
+                       const double* h_tau0, int64_t G, uint64_t* d_counts,
+                       double* h_tau_hat, void* stream);
+
+/*
+ * rr_draw_balance_batched -- many independent Monte Carlo pools in one persistent launch
+ * (section 2.1 "Batched processing").  Problem i uses handle P[i], seed seeds[i], draws
+ * [key_begin, key_begin + num_draws) and the same mode / q_or_a / precision for all.
+ * Outputs: d_keys[i], d_M[i] (device pointers, capacity entries each) and h_counts[i].
+ * Results are identical to nprob calls of rr_draw_balance.
+ */
+rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob, const uint64_t* seeds,
+                                  uint64_t key_begin, uint64_t num_draws, int mode,
+                                  double q_or_a, int precision, uint64_t* const* d_keys,
+                                  double* const* d_M, uint64_t capacity, uint64_t* h_counts,
+                                  void* stream);
+
+/* Timing of the last rr_draw_balance / rr_draw_exact / rr_draw_balance_batched call on
+ * this thread, measured with HIP events on its stream: total milliseconds and the
+ * milliseconds spent in the fused generate-and-contract kernel; number of its launches. */
+rr_status rr_last_timing(double* total_ms, double* draw_kernel_ms, int64_t* draw_launches,
+                         uint64_t* band_size);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RR_H */

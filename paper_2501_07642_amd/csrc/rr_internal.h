@@ -1,0 +1,357 @@
+// Internal declarations of librr: problem handle, device helpers shared by the kernels.
+//
+// Target: gfx950 (CDNA4), wave64.  Every kernel is written for 64-lane wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rr.h"
+
+namespace rr {
+
+// ---------------------------------------------------------------------------------------
+// Error plumbing (host).
+void set_error(const std::string& msg);
+#define RR_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::rr::set_error(std::string(#call) + ": " + hipGetErrorString(e_));        \
+            return RR_E_DEVICE;                                                        \
+        }                                                                              \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------
+// Layout constants.
+constexpr int kWave = 64;
+constexpr int kUnitsPerChunk = 256;   // one Philox block per lane yields 4 x 64 units
+constexpr int kKStep = 16;            // units per MFMA K step (32x32x16 BF16)
+constexpr int kColBlock = 32;         // covariates per MFMA row block
+constexpr int kRecordU4 = 128;        // uint4 per operand record: 2 planes x 64 lanes x 16 B
+constexpr int kMaxS = RR_MAX_N / kUnitsPerChunk;   // 16
+
+// Host-side description of a prepared problem.
+struct Problem {
+    int device = 0;
+    int64_t n = 0, d = 0, n1 = 0, n0 = 0;
+    double ridge_rel = 0, lambda = 0;
+    int S = 0;             // 256-unit chunks per draw: ceil(n / 256)
+    int wstride = 0;       // uint32 words per draw bitmask in the internal layout: 8 * S
+    int64_t ks = 0;        // K steps of 16 units: ceil(n / 16)
+    int64_t ncb = 0;       // covariate blocks of 32 (padded)
+    double scale = 0;      // n / (n1 n0)
+    // device buffers
+    double* X64 = nullptr;     // n x d whitened, centred covariates X~ (FP64, row-major)
+    double* L = nullptr;       // d x d Cholesky factor of S_lam (lower)
+    double* mu = nullptr;      // d column means
+    uint4* op_split = nullptr; // ks * ncb records: BF16 hi / lo planes
+    uint4* op_f32 = nullptr;   // ks * ncb records: FP32 planes
+    float* cabs = nullptr;     // 32 * ncb column sums of |X~| (rounded up; 0 for pads)
+    // workspace for the draw pipeline (grown on demand)
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+
+// ---------------------------------------------------------------------------------------
+// Kernel argument blocks (shared by the draw kernels and the pipeline).
+struct DrawArgs {
+    const uint4* op;          // operand records, ks * ncb records of kRecordU4 uint4
+    const float* cabs;        // 32 * ncb
+    const uint64_t* binom;    // exact mode: C(i, t), i <= 64, t <= 32
+    const uint64_t* keylist;  // list generation: keys of the draws
+    uint64_t seed, key_begin, num;
+    int n, n1, ks, ncb;
+    float scale;              // n / (n1 n0)
+    float two_kappa;          // 2 * kappa: |G32_j - G_j| <= kappa * cabs_j
+    float csq;                // kappa^2 * sum_j cabs_j^2
+    float gamma_ss;           // relative bound of the FP32 sum of squares and the scaling
+    float safety;             // multiplies the assembled bound
+    const float* U;           // append iff lo <= *U; null appends every draw
+    uint64_t* cand_key;
+    float* cand_hi;
+    float* cand_lo;
+    float* cand_m;
+    uint32_t* cand_count;
+    uint32_t cand_cap;
+    float* out_m32;           // evaluation mode (non-null): per-draw outputs, no prefilter
+    float* out_err;
+};
+
+struct RecheckArgs {
+    const double* X64;        // n x d, row-major
+    const uint64_t* keys;     // keys of the draws
+    const uint32_t* count;    // number of entries (device)
+    uint64_t seed;
+    const uint64_t* binom;
+    int n, n1, d;
+    double scale;
+    double* out;              // M64 per entry
+};
+
+}  // namespace rr
+
+struct rr_problem {
+    rr::Problem P;
+};
+
+namespace rr {
+
+// ---------------------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon et al., SC'11): counter (c0..c3), key (k0, k1); per round the
+// products M0*c0 and M1*c2 give (hi1^c1^k0, lo1, hi0^c3^k1, lo0); the key advances by the
+// Weyl constants between rounds.
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+__device__ __forceinline__ void philox_block(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                             uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Wave helpers.
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// inclusive prefix sum across the wave
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, 64);
+        if (l >= o) v += t;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Monte Carlo draw: the n1 units with the smallest (u_i, i) become treated.  Unit
+// i = 256 s + 64 r + lane reads word r of Philox block 64 s + lane under counter
+// (block, 0, lo32(key), hi32(key)) and the pool seed as Philox key.  The wave computes the
+// n1-th smallest pair exactly: a 256-bin histogram of the top byte (LDS atomics), then
+// narrower bytes while the selected bin still holds more than 64 values, then an explicit
+// ranking of the few values left, then index order among values equal to the threshold.
+// Output: bitmask words (bit i%32 of word i/32), written by lane 0 to `out` (8 S words).
+//
+// `hist` is a wave-private 256-word LDS array, `list` a wave-private 64-entry LDS array.
+template <int S>
+__device__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint32_t* hist,
+                            uint2* list, uint32_t* out) {
+    const int lane = lane_id();
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t blo = (uint32_t)key, bhi = (uint32_t)(key >> 32);
+    const int chunks = (n + kUnitsPerChunk - 1) / kUnitsPerChunk;
+    uint32_t u[S][4];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (s < chunks) {
+            uint32_t c0 = 64u * s + lane, c1 = 0, c2 = blo, c3 = bhi;
+            philox_block(c0, c1, c2, c3, k0, k1);
+            u[s][0] = c0; u[s][1] = c1; u[s][2] = c2; u[s][3] = c3;
+        } else {
+            u[s][0] = u[s][1] = u[s][2] = u[s][3] = 0xFFFFFFFFu;
+        }
+    }
+    auto valid = [&](int s, int r) { return 256 * s + 64 * r + lane < n; };
+
+    // Exact n1-th smallest value, byte by byte from the top.
+    uint32_t prefix = 0;     // bytes fixed so far (above `shift`)
+    int need = n1;           // rank (1-based) of the target among values matching prefix
+    int below = 0;           // valid values strictly below the current prefix range
+    int shift = 24;
+    int bin_count = 0;
+    for (;;) {
+        reinterpret_cast<uint4*>(hist)[lane] = make_uint4(0, 0, 0, 0);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        const uint32_t hi_mask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s < chunks) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (valid(s, r) && ((u[s][r] & hi_mask) == (prefix & hi_mask)))
+                        atomicAdd(&hist[(u[s][r] >> shift) & 255u], 1u);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint4 c = reinterpret_cast<const uint4*>(hist)[lane];
+        const uint32_t tot = c.x + c.y + c.z + c.w;
+        const uint32_t incl = wave_incl_scan(tot);
+        const uint32_t excl = incl - tot;
+        // bin j of this lane holds the target iff cum_before < need <= cum_before + cnt
+        int hit = -1;
+        uint32_t cb = 0, cnt = 0;
+        {
+            uint32_t run = excl;
+            const uint32_t cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (hit < 0 && run < (uint32_t)need && (uint32_t)need <= run + cc[j]) {
+                    hit = j; cb = run; cnt = cc[j];
+                }
+                run += cc[j];
+            }
+        }
+        const uint64_t m = ballot(hit >= 0);
+        const int src = (int)__builtin_ctzll(m);
+        const int bin = __shfl(4 * lane + hit, src, 64);
+        const int cbs = (int)__shfl(cb, src, 64);
+        bin_count = (int)__shfl(cnt, src, 64);
+        below += cbs;
+        need -= cbs;
+        prefix |= (uint32_t)bin << shift;
+        if (bin_count <= 64 || shift == 0) break;
+        shift -= 8;
+    }
+
+    // Threshold value ustar, count of valid values below it, how many equal ones to take.
+    uint32_t ustar;
+    int take, eq_total;
+    if (shift == 0) {
+        ustar = prefix;
+        take = need;
+        eq_total = bin_count;
+        // below already counts everything strictly below ustar
+    } else {
+        // Collect the <= 64 values of the selected bin into the list.
+        const uint32_t mask_hi = 0xFFFFFFFFu << shift;
+        int base = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s < chunks) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool f = valid(s, r) && ((u[s][r] & mask_hi) == prefix);
+                    const uint64_t bm = ballot(f);
+                    if (bm) {
+                        if (f) {
+                            const int pos = base + (int)__builtin_amdgcn_mbcnt_hi(
+                                                       (uint32_t)(bm >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+                            list[pos] = make_uint2(u[s][r], 0u);
+                        }
+                        base += __builtin_popcountll(bm);
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        int lt = 0, le = 0;
+        const uint32_t mine = lane < bin_count ? list[lane].x : 0u;
+        for (int t = 0; t < bin_count; ++t) {
+            const uint32_t v = list[t].x;
+            lt += v < mine;
+            le += v <= mine;
+        }
+        const bool is_t = lane < bin_count && lt < need && need <= le;
+        const uint64_t mt = ballot(is_t);
+        const int src = (int)__builtin_ctzll(mt);
+        ustar = __shfl(mine, src, 64);
+        const int lts = __shfl(lt, src, 64);
+        const int les = __shfl(le, src, 64);
+        below += lts;
+        take = need - lts;
+        eq_total = les - lts;
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // Index threshold among values equal to ustar (only when some must be left out).
+    int istar = 0x7FFFFFFF;
+    if (take < eq_total) {
+        int left = take;
+        bool found = false;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (!found && s < chunks) {
+                    uint64_t bm = ballot(valid(s, r) && u[s][r] == ustar);
+                    const int pc = __builtin_popcountll(bm);
+                    if (left <= pc) {
+                        for (int q = 1; q < left; ++q) bm &= bm - 1;
+                        istar = 256 * s + 64 * r + (int)__builtin_ctzll(bm);
+                        found = true;
+                    } else {
+                        left -= pc;
+                    }
+                }
+            }
+        }
+    }
+
+    // Treated indicator and bitmask words.
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        uint32_t w[8];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int unit = 256 * s + 64 * r + lane;
+            const bool t = s < chunks && valid(s, r) &&
+                           (u[s][r] < ustar || (u[s][r] == ustar && unit <= istar));
+            const uint64_t bm = ballot(t);
+            w[2 * r] = (uint32_t)bm;
+            w[2 * r + 1] = (uint32_t)(bm >> 32);
+        }
+        if (lane == 0) {
+            reinterpret_cast<uint4*>(out + 8 * s)[0] = make_uint4(w[0], w[1], w[2], w[3]);
+            reinterpret_cast<uint4*>(out + 8 * s)[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        }
+    }
+    (void)below;
+}
+
+// ---------------------------------------------------------------------------------------
+// Exact enumeration: colex unranking, r = sum_t C(i_t, t).  One lane per draw; n <= 64.
+// binom[i * 33 + t] = C(i, t) for i <= 64, t <= 32 (0 where undefined), symmetric use of t.
+__device__ __forceinline__ uint64_t colex_unrank_mask(uint64_t r, int n, int n1,
+                                                      const uint64_t* binom) {
+    // C(i, t) for t > 32 via symmetry C(i, i - t); table holds t <= 32.
+    auto C = [&](int i, int t) -> uint64_t {
+        if (t < 0 || t > i) return 0;
+        int tt = t <= i - t ? t : i - t;
+        return binom[i * 33 + tt];
+    };
+    uint64_t mask = 0;
+    int hi = n;
+    for (int t = n1; t >= 1; --t) {
+        int i = hi - 1;
+        while (C(i, t) > r) --i;
+        mask |= 1ull << i;
+        r -= C(i, t);
+        hi = i;
+    }
+    return mask;
+}
+
+}  // namespace rr

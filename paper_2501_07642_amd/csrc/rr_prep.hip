@@ -1,0 +1,342 @@
+// rr_prepare: whitening of the covariates in FP64 on the device.
+//
+// Section 2.2 assumes covariates whitened so that Sigma_X = I, and the Appendix A remark
+// maps a general Sigma_X to that case through X~ = X Sigma_X^-1/2, so that
+// M = Delta^T Sigma_X^-1 Delta = ||Delta~||^2.  Here Sigma_X is the sample covariance S over
+// all n units (denominator n - 1) plus a ridge lambda I, lambda = ridge_rel tr(S) / d; the
+// square root is its Cholesky factor L (S_lam = L L^T), and X~ = (X - 1 mu^T) L^-T.
+//
+// Steps (all FP64): column means; centring; S = Xc^T Xc / (n-1) (tiled GEMM); ridge;
+// blocked right-looking Cholesky (diagonal block in LDS, row solves for the panel, GEMM
+// update of the trailing matrix); X~ by blocked forward substitution; BF16 hi/lo and FP32
+// operand records for the W X~ contraction; column sums of |X~| for the error bound.
+#include <cmath>
+#include <cstring>
+
+#include "rr_internal.h"
+
+namespace rr {
+
+constexpr int kNB = 32;   // Cholesky / solve block
+
+__global__ void mean_center_kernel(const void* X, int fp32, int64_t n, int64_t d, int64_t ldx,
+                                   double* mu, double* Xc) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= d) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s += fp32 ? (double)((const float*)X)[i * ldx + j] : ((const double*)X)[i * ldx + j];
+    const double m = s / (double)n;
+    mu[j] = m;
+    for (int64_t i = 0; i < n; ++i) {
+        const double x = fp32 ? (double)((const float*)X)[i * ldx + j] : ((const double*)X)[i * ldx + j];
+        Xc[i * d + j] = x - m;
+    }
+}
+
+// C[m, c] = beta * C[m, c] + alpha * sum_k A(m, k) B(c, k), A(m,k) = A[m*sam + k*sak],
+// B(c,k) = B[c*sbn + k*sbk], C row-major with leading dimension ldc.  64x64 tiles.
+__global__ __launch_bounds__(256) void dgemm_nt_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                       const double* A, int64_t sam, int64_t sak,
+                                                       const double* B, int64_t sbn, int64_t sbk,
+                                                       double beta, double* C, int64_t ldc) {
+    __shared__ double As[16][65];
+    __shared__ double Bs[16][65];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t m0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    double acc[4][4] = {};
+    for (int64_t k0 = 0; k0 < K; k0 += 16) {
+        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+            const int kk = e & 15, r = e >> 4;
+            const int64_t k = k0 + kk;
+            As[kk][r] = (m0 + r < M && k < K) ? A[(m0 + r) * sam + k * sak] : 0.0;
+            Bs[kk][r] = (c0 + r < N && k < K) ? B[(c0 + r) * sbn + k * sbk] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) b[i] = Bs[kk][tx + 16 * i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[i][q] = fma(a[i], b[q], acc[i][q]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t m = m0 + ty + 16 * i, c = c0 + tx + 16 * q;
+            if (m < M && c < N) {
+                double* p = C + m * ldc + c;
+                *p = (beta == 0.0 ? 0.0 : beta * *p) + alpha * acc[i][q];
+            }
+        }
+}
+
+// tr(S), max S_jj, then S_jj += lambda with lambda = ridge_rel * tr(S) / d.
+__global__ void ridge_kernel(double* S, int64_t d, double ridge_rel, double* out /*lambda, maxdiag*/) {
+    __shared__ double st[256], sm[256];
+    double t = 0.0, m = 0.0;
+    for (int64_t j = threadIdx.x; j < d; j += 256) {
+        const double v = S[j * d + j];
+        t += v;
+        m = fmax(m, v);
+    }
+    st[threadIdx.x] = t;
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            st[threadIdx.x] += st[threadIdx.x + o];
+            sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    const double lam = ridge_rel * st[0] / (double)d;
+    for (int64_t j = threadIdx.x; j < d; j += 256) S[j * d + j] += lam;
+    if (threadIdx.x == 0) {
+        out[0] = lam;
+        out[1] = sm[0];
+    }
+}
+
+// Unblocked Cholesky of the nb x nb diagonal block at (k0, k0); pivots recorded.
+__global__ void potrf_diag_kernel(double* A, int64_t d, int64_t k0, int nb, double* pivots, int* bad) {
+    __shared__ double T[kNB][kNB + 1];
+    const int tx = threadIdx.x;
+    for (int e = tx; e < nb * nb; e += blockDim.x) T[e / nb][e % nb] = A[(k0 + e / nb) * d + k0 + e % nb];
+    __syncthreads();
+    for (int p = 0; p < nb; ++p) {
+        if (tx == 0) {
+            const double v = T[p][p];
+            pivots[k0 + p] = v;
+            if (!(v > 0.0)) *bad = 1;
+            T[p][p] = v > 0.0 ? sqrt(v) : 1.0;
+        }
+        __syncthreads();
+        if (tx > p && tx < nb) T[tx][p] /= T[p][p];
+        __syncthreads();
+        if (tx > p && tx < nb)
+            for (int c = p + 1; c <= tx; ++c) T[tx][c] -= T[tx][p] * T[c][p];
+        __syncthreads();
+    }
+    for (int e = tx; e < nb * nb; e += blockDim.x) {
+        const int r = e / nb, c = e % nb;
+        A[(k0 + r) * d + k0 + c] = c <= r ? T[r][c] : 0.0;
+    }
+}
+
+// Rows r0..r0+rows-1 of the nb-column block at column k0 of Mtx (leading dim ldm) are
+// replaced by x with x L11^T = row, L11 the nb x nb lower block of L at (k0, k0).
+__global__ void trsm_rows_kernel(double* Mtx, int64_t ldm, int64_t r0, int64_t rows, int64_t col0,
+                                 const double* L, int64_t d, int64_t k0, int nb) {
+    __shared__ double T[kNB][kNB + 1];
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) T[e / nb][e % nb] = L[(k0 + e / nb) * d + k0 + e % nb];
+    __syncthreads();
+    const int64_t r = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= r0 + rows) return;
+    double x[kNB];
+    double* row = Mtx + r * ldm + col0;
+    for (int p = 0; p < nb; ++p) {
+        double v = row[p];
+        for (int t = 0; t < p; ++t) v -= x[t] * T[p][t];
+        x[p] = v / T[p][p];
+    }
+    for (int p = 0; p < nb; ++p) row[p] = x[p];
+}
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Operand records.  Record (k, cb) (index k * ncb + cb) covers units 16k..16k+15 and
+// covariates 32cb..32cb+31 in 2 planes of 64 lanes x 16 bytes; lane l = c + 32h:
+//   split: plane 0 = BF16 hi, plane 1 = BF16 lo of X~(16k + 8h + e, 32cb + c), e = 0..7;
+//   fp32:  plane p holds X~(16k + 8p + 2q + h, 32cb + c), q = 0..3.
+__global__ void operands_kernel(const double* X, int64_t n, int64_t d, int64_t ks, int64_t ncb,
+                                uint4* op_split, uint4* op_f32) {
+    const int64_t rec = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t k = rec / ncb, cb = rec % ncb;
+    const int c = lane & 31, h = lane >> 5;
+    const int64_t col = 32 * cb + c;
+    auto x = [&](int64_t unit) -> double {
+        return (unit < n && col < d) ? X[unit * d + col] : 0.0;
+    };
+    uint32_t hi[4], lo[4];
+    for (int e = 0; e < 8; e += 2) {
+        uint16_t hv[2], lv[2];
+        for (int q = 0; q < 2; ++q) {
+            const double v = x(16 * k + 8 * h + e + q);
+            const uint16_t hb = bf16_rne((float)v);
+            const double r = v - (double)bf16_to_float(hb);
+            hv[q] = hb;
+            lv[q] = bf16_rne((float)r);
+        }
+        hi[e / 2] = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
+        lo[e / 2] = (uint32_t)lv[0] | ((uint32_t)lv[1] << 16);
+    }
+    op_split[rec * kRecordU4 + lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+    op_split[rec * kRecordU4 + 64 + lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    for (int p = 0; p < 2; ++p) {
+        float f[4];
+        for (int q = 0; q < 4; ++q) f[q] = (float)x(16 * k + 8 * p + 2 * q + h);
+        op_f32[rec * kRecordU4 + 64 * p + lane] =
+            make_uint4(__float_as_uint(f[0]), __float_as_uint(f[1]), __float_as_uint(f[2]), __float_as_uint(f[3]));
+    }
+}
+
+// cabs_j = sum_i |X~_ij| rounded up to float; 0 for padded columns.
+__global__ void cabs_kernel(const double* X, int64_t n, int64_t d, int64_t dpad, float* cabs) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= dpad) return;
+    if (j >= d) {
+        cabs[j] = 0.f;
+        return;
+    }
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += fabs(X[i * d + j]);
+    s *= 1.0 + 1e-12;   // cover the FP64 rounding of the sum itself
+    float f = (float)s;
+    if ((double)f < s) f = nextafterf(f, INFINITY);
+    cabs[j] = f;
+}
+
+static hipError_t gemm_nt(hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                          int64_t sam, int64_t sak, const double* B, int64_t sbn, int64_t sbk, double beta,
+                          double* C, int64_t ldc) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
+    hipLaunchKernelGGL(dgemm_nt_kernel, grid, dim3(256), 0, st, M, N, K, alpha, A, sam, sak, B, sbn, sbk, beta, C, ldc);
+    return hipGetLastError();
+}
+
+int pow2_chunks(int n);
+
+rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_t ldx, int64_t n1,
+                       double ridge_rel, hipStream_t st, rr_problem** out) {
+    if (!dX || !out || n < 2 || d < 1 || ldx < d || n1 < 1 || n1 > n - 1 || !(ridge_rel >= 0.0) ||
+        (x_dtype != RR_X_FP64 && x_dtype != RR_X_FP32)) {
+        set_error("rr_prepare: invalid argument");
+        return RR_E_ARG;
+    }
+    if (n > RR_MAX_N) {
+        set_error("rr_prepare: n exceeds RR_MAX_N");
+        return RR_E_UNSUPPORTED;
+    }
+    auto* h = new rr_problem();
+    Problem& P = h->P;
+    RR_HIP(hipGetDevice(&P.device));
+    P.n = n;
+    P.d = d;
+    P.n1 = n1;
+    P.n0 = n - n1;
+    P.ridge_rel = ridge_rel;
+    P.S = pow2_chunks((int)n);
+    P.wstride = 8 * P.S;
+    P.ks = (n + kKStep - 1) / kKStep;
+    const int64_t cbq = 4;
+    P.ncb = (((d + kColBlock - 1) / kColBlock + cbq - 1) / cbq) * cbq;
+    P.scale = (double)n / ((double)n1 * (double)(n - n1));
+    const int64_t dpad = 32 * P.ncb;
+
+    double *S = nullptr, *piv = nullptr, *scal = nullptr;
+    int* bad = nullptr;
+    auto fail = [&](rr_status s) {
+        hipFree(S);
+        hipFree(piv);
+        hipFree(scal);
+        hipFree(bad);
+        rr_free(h);
+        return s;
+    };
+#define RR_PHIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            set_error(std::string("rr_prepare: ") + #call + ": " + hipGetErrorString(e_)); \
+            return fail(RR_E_DEVICE);                                                     \
+        }                                                                                 \
+    } while (0)
+    RR_PHIP(hipMalloc(&P.X64, sizeof(double) * n * d));
+    RR_PHIP(hipMalloc(&P.L, sizeof(double) * d * d));
+    RR_PHIP(hipMalloc(&P.mu, sizeof(double) * d));
+    RR_PHIP(hipMalloc(&P.op_split, sizeof(uint4) * kRecordU4 * P.ks * P.ncb));
+    RR_PHIP(hipMalloc(&P.op_f32, sizeof(uint4) * kRecordU4 * P.ks * P.ncb));
+    RR_PHIP(hipMalloc(&P.cabs, sizeof(float) * dpad));
+    RR_PHIP(hipMalloc(&piv, sizeof(double) * d));
+    RR_PHIP(hipMalloc(&scal, sizeof(double) * 2));
+    RR_PHIP(hipMalloc(&bad, sizeof(int)));
+    RR_PHIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+
+    hipLaunchKernelGGL(mean_center_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, dX, x_dtype,
+                       n, d, ldx, P.mu, P.X64);
+    RR_PHIP(hipGetLastError());
+    // S = Xc^T Xc / (n - 1) into L's buffer, then factor in place.
+    double* A = P.L;
+    RR_PHIP(gemm_nt(st, d, d, n, 1.0 / (double)(n - 1), P.X64, 1, d, P.X64, 1, d, 0.0, A, d));
+    hipLaunchKernelGGL(ridge_kernel, dim3(1), dim3(256), 0, st, A, d, ridge_rel, scal);
+    RR_PHIP(hipGetLastError());
+    for (int64_t k0 = 0; k0 < d; k0 += kNB) {
+        const int nb = (int)std::min<int64_t>(kNB, d - k0);
+        hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(kNB), 0, st, A, d, k0, nb, piv, bad);
+        RR_PHIP(hipGetLastError());
+        const int64_t r0 = k0 + nb, rows = d - r0;
+        if (rows > 0) {
+            hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((rows + 127) / 128)), dim3(128), 0, st, A, d, r0,
+                               rows, k0, A, d, k0, nb);
+            RR_PHIP(hipGetLastError());
+            RR_PHIP(gemm_nt(st, rows, rows, nb, -1.0, A + r0 * d + k0, d, 1, A + r0 * d + k0, d, 1, 1.0,
+                            A + r0 * d + r0, d));
+        }
+    }
+    double hs[2];
+    std::vector<double> hp((size_t)d);
+    int hbad = 0;
+    RR_PHIP(hipMemcpyAsync(hs, scal, sizeof(hs), hipMemcpyDeviceToHost, st));
+    RR_PHIP(hipMemcpyAsync(hp.data(), piv, sizeof(double) * d, hipMemcpyDeviceToHost, st));
+    RR_PHIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    RR_PHIP(hipStreamSynchronize(st));
+    P.lambda = hs[0];
+    double minpiv = INFINITY;
+    for (double v : hp) minpiv = std::min(minpiv, v);
+    if (hbad || !(minpiv >= 1e-10 * hs[1])) {
+        set_error("rr_prepare: covariance is singular (use ridge_rel > 0)");
+        return fail(RR_E_SINGULAR);
+    }
+    // upper triangle of L to zero (the factor is lower triangular)
+    // X~ = Xc L^-T by column blocks: X[:, J] -= X~[:, <J] L[J, <J]^T, then solve with L[J, J].
+    for (int64_t j0 = 0; j0 < d; j0 += kNB) {
+        const int nb = (int)std::min<int64_t>(kNB, d - j0);
+        if (j0 > 0) RR_PHIP(gemm_nt(st, n, nb, j0, -1.0, P.X64, d, 1, A + j0 * d, d, 1, 1.0, P.X64 + j0, d));
+        hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, P.X64, d, 0, n,
+                           j0, A, d, j0, nb);
+        RR_PHIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(operands_kernel, dim3((unsigned)(P.ks * P.ncb)), dim3(64), 0, st, P.X64, n, d, P.ks, P.ncb,
+                       P.op_split, P.op_f32);
+    RR_PHIP(hipGetLastError());
+    hipLaunchKernelGGL(cabs_kernel, dim3((unsigned)((dpad + 255) / 256)), dim3(256), 0, st, P.X64, n, d, dpad,
+                       P.cabs);
+    RR_PHIP(hipGetLastError());
+    RR_PHIP(hipStreamSynchronize(st));
+    hipFree(S);
+    hipFree(piv);
+    hipFree(scal);
+    hipFree(bad);
+#undef RR_PHIP
+    *out = h;
+    return RR_OK;
+}
+
+}  // namespace rr

@@ -1,0 +1,903 @@
+// Acceptance: streaming prefilter, exact selection over FP32 bounds, FP64 recheck of the
+// guard band, key-ordered tie rule, sorted key-only output.  Also the C-ABI entry points
+// of the draw pipeline.
+//
+// Acceptance rules (section 2.2; Appendix A part C): threshold, M <= a; q-quantile, the
+// k = ceil(q N (1 - 1e-12)) smallest M, values within a relative eps = 1e-10 of the k-th
+// smallest ordered by key.
+//
+// Every draw carries an FP32 value m32 and a rigorous error bound e, so the FP64 value lies
+// in [lo, hi] = [m32 - e, m32 + e] (both padded outward).  With T_hi / T_lo the k-th smallest
+// hi / lo, the k-th smallest M lies in [T_lo, T_hi]; a draw with hi < T_lo (1 - eps) is
+// accepted outright, one with lo > T_hi (1 + eps) is rejected outright, and the rest -- the
+// guard band -- are recomputed in FP64 and the rule is applied to those values.  While
+// streaming, a draw is kept as a candidate only if lo <= U, U = (1 + eps) x the running
+// T_hi, which never discards a draw the final selection could need.
+#include <algorithm>
+#include <cstddef>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "rr_internal.h"
+
+namespace rr {
+
+hipError_t launch_draw(int S, int prec, bool exact, bool from_list, const DrawArgs& a, int grid, hipStream_t st);
+hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hipStream_t st);
+hipError_t launch_regen(int S, bool exact, const uint64_t* keys, uint64_t K, uint64_t seed, int n, int n1,
+                        const uint64_t* binom, uint32_t* out, int nw, int grid, hipStream_t st);
+int draw_tile();
+int draw_cb();
+
+
+constexpr double kEpsTie = 1e-10;
+constexpr double kQFuzz = 1e-12;
+
+// ---------------------------------------------------------------------------------------
+// Error state and timing.
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+struct Timing {
+    double total_ms = 0, draw_ms = 0;
+    int64_t launches = 0;
+    uint64_t band = 0;
+};
+static thread_local Timing g_timing;
+
+// ---------------------------------------------------------------------------------------
+// Device control block.
+struct Ctl {
+    uint32_t cand_count;
+    uint32_t overflow;
+    float U;
+    uint32_t sel_prefix[2];
+    uint32_t sel_krem[2];
+    uint32_t sel_fail;
+    uint32_t k;
+    uint32_t nL;          // accepted outright (written into the accepted list)
+    uint32_t band_count;
+    uint32_t acc_count;
+    uint32_t guard_fail;
+    uint32_t hist[2][256];
+};
+
+// ---------------------------------------------------------------------------------------
+// Binomial table for colex unranking (per device, created once).
+const uint64_t* binom_table(int dev) {
+    static std::mutex mu;
+    static uint64_t* tab[64] = {};
+    std::lock_guard<std::mutex> g(mu);
+    if (dev < 0 || dev >= 64) return nullptr;
+    if (!tab[dev]) {
+        std::vector<uint64_t> h(65 * 33, 0);
+        for (int i = 0; i <= 64; ++i) {
+            uint64_t c = 1;
+            for (int t = 0; t <= 32 && t <= i; ++t) {
+                h[i * 33 + t] = c;
+                // C(i, t+1) = C(i, t) * (i - t) / (t + 1), exact in 128-bit
+                c = (uint64_t)((unsigned __int128)c * (uint64_t)(i - t) / (uint64_t)(t + 1));
+            }
+        }
+        uint64_t* p = nullptr;
+        if (hipMalloc(&p, h.size() * sizeof(uint64_t)) != hipSuccess) return nullptr;
+        if (hipMemcpy(p, h.data(), h.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+        tab[dev] = p;
+    }
+    return tab[dev];
+}
+
+const uint64_t* binom_table_ext(int dev) { return binom_table(dev); }
+
+static bool binom_exact(int64_t n, int64_t k, uint64_t* out) {
+    unsigned __int128 c = 1;
+    for (int64_t t = 0; t < k; ++t) {
+        c = c * (unsigned __int128)(n - t) / (unsigned __int128)(t + 1);
+        if (c > ((unsigned __int128)1 << 64) - 1) return false;
+    }
+    *out = (uint64_t)c;
+    return true;
+}
+
+// ---------------------------------------------------------------------------------------
+// Kernels: radix selection of the k-th smallest of two float arrays (bit patterns of
+// non-negative floats order like the values), one 8-bit digit per pass.
+__global__ void sel_hist_kernel(const float* a0, const float* a1, const uint32_t* count, Ctl* ctl, int shift) {
+    __shared__ uint32_t h[2][256];
+    for (int i = threadIdx.x; i < 512; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t n = *count;
+    const uint32_t m = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+    const uint32_t p0 = ctl->sel_prefix[0] & m, p1 = ctl->sel_prefix[1] & m;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t x0 = __float_as_uint(a0[i]);
+        const uint32_t x1 = __float_as_uint(a1[i]);
+        if ((x0 & m) == p0) atomicAdd(&h[0][(x0 >> shift) & 255u], 1u);
+        if ((x1 & m) == p1) atomicAdd(&h[1][(x1 >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 512; i += blockDim.x) {
+        const uint32_t v = (&h[0][0])[i];
+        if (v) atomicAdd(&ctl->hist[0][0] + i, v);
+    }
+}
+
+__global__ void sel_scan_kernel(Ctl* ctl, int shift) {
+    // one wave per selection
+    const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t need = ctl->sel_krem[s];
+    const uint4 c = reinterpret_cast<const uint4*>(ctl->hist[s])[lane];
+    const uint32_t tot = c.x + c.y + c.z + c.w;
+    const uint32_t incl = wave_incl_scan(tot);
+    uint32_t run = incl - tot;
+    const uint32_t cc[4] = {c.x, c.y, c.z, c.w};
+    int hit = -1;
+    uint32_t cb = 0;
+    for (int j = 0; j < 4; ++j) {
+        if (hit < 0 && run < need && need <= run + cc[j]) {
+            hit = j;
+            cb = run;
+        }
+        run += cc[j];
+    }
+    const uint64_t m = __ballot(hit >= 0);
+    if (m == 0) {
+        if (lane == 0) ctl->sel_fail = 1;
+    } else {
+        const int src = (int)__builtin_ctzll(m);
+        const int bin = __shfl(4 * lane + hit, src, 64);
+        const uint32_t cbs = __shfl(cb, src, 64);
+        if (lane == 0) {
+            ctl->sel_prefix[s] |= (uint32_t)bin << shift;
+            ctl->sel_krem[s] = need - cbs;
+        }
+    }
+    reinterpret_cast<uint4*>(ctl->hist[s])[lane] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void sel_init_kernel(Ctl* ctl) {
+    ctl->sel_prefix[0] = ctl->sel_prefix[1] = 0;
+    ctl->sel_krem[0] = ctl->sel_krem[1] = ctl->k;
+}
+
+__device__ __forceinline__ float f32_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+__global__ void update_U_kernel(Ctl* ctl) {
+    const double thi = (double)__uint_as_float(ctl->sel_prefix[0]);
+    const float u = f32_up(thi * (1.0 + kEpsTie));
+    ctl->U = fminf(ctl->U, u);
+}
+
+// Outright acceptances go to the accepted list; guard-band members to the band list.
+__global__ void classify_kernel(const uint64_t* ck, const float* chi, const float* clo, const float* cm,
+                                Ctl* ctl, int mode, double a, uint64_t* acc_key, double* acc_m,
+                                uint8_t* acc_flag, uint32_t acc_cap, uint64_t* band_key,
+                                uint32_t band_cap) {
+    const uint32_t n = ctl->cand_count;
+    double lo_cut, hi_cut;
+    if (mode == RR_MODE_QUANTILE) {
+        lo_cut = (double)__uint_as_float(ctl->sel_prefix[1]) * (1.0 - kEpsTie);
+        hi_cut = (double)__uint_as_float(ctl->sel_prefix[0]) * (1.0 + kEpsTie);
+    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double hi = chi[i], lo = clo[i];
+        bool acc, band;
+        if (mode == RR_MODE_QUANTILE) {
+            acc = hi < lo_cut;
+            band = !acc && lo <= hi_cut && hi >= lo_cut;
+        } else {
+            acc = hi <= a;
+            band = !acc && lo <= a;
+        }
+        if (acc) {
+            const uint32_t p = atomicAdd(&ctl->acc_count, 1u);
+            atomicAdd(&ctl->nL, 1u);
+            if (p < acc_cap) {
+                acc_key[p] = ck[i];
+                acc_m[p] = (double)cm[i];
+                acc_flag[p] = 0;
+            }
+        } else if (band) {
+            const uint32_t p = atomicAdd(&ctl->band_count, 1u);
+            if (p < band_cap) band_key[p] = ck[i];
+        }
+    }
+}
+
+__global__ void cap_band_kernel(Ctl* ctl, uint32_t cap) {
+    if (ctl->band_count > cap) {
+        ctl->overflow = 1;
+        ctl->band_count = cap;
+    }
+}
+
+// Single-workgroup selection among the guard band (FP64 values) and final acceptance.
+__device__ uint64_t block_select_u64(const uint64_t* v, const uint8_t* ok, uint32_t n, uint32_t k,
+                                     uint32_t* hist) {
+    // k-th smallest (1-based) of v[i] over i with ok[i] (ok null = all)
+    uint64_t prefix = 0;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        const uint64_t m = shift == 56 ? 0ull : (~0ull << (shift + 8));
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            if (ok && !ok[i]) continue;
+            const uint64_t x = v[i];
+            if ((x & m) == (prefix & m)) atomicAdd(&hist[(x >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        __shared__ uint32_t s_bin, s_below;
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            int bin = 255;
+            for (int b = 0; b < 256; ++b) {
+                if (run + hist[b] >= k) {
+                    bin = b;
+                    break;
+                }
+                run += hist[b];
+            }
+            s_bin = (uint32_t)bin;
+            s_below = run;
+        }
+        __syncthreads();
+        prefix |= (uint64_t)s_bin << shift;
+        k -= s_below;
+        __syncthreads();
+    }
+    return prefix;
+}
+
+__global__ __launch_bounds__(1024) void band_accept_kernel(const uint64_t* bkey, const double* bm, uint8_t* work,
+                                                           Ctl* ctl, int mode, double a, uint64_t* acc_key,
+                                                           double* acc_m, uint8_t* acc_flag, uint32_t acc_cap) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_cnt;
+    const uint32_t nb = ctl->band_count;
+    if (mode == RR_MODE_THRESHOLD) {
+        for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
+            if (bm[i] <= a) {
+                const uint32_t p = atomicAdd(&ctl->acc_count, 1u);
+                if (p < acc_cap) {
+                    acc_key[p] = bkey[i];
+                    acc_m[p] = bm[i];
+                    acc_flag[p] = 1;
+                }
+            }
+        }
+        return;
+    }
+    const int64_t need = (int64_t)ctl->k - (int64_t)ctl->nL;
+    if (need < 1 || (int64_t)nb < need) {
+        if (threadIdx.x == 0) ctl->guard_fail = 1;
+        return;
+    }
+    const uint64_t* bits = reinterpret_cast<const uint64_t*>(bm);
+    const double t = __longlong_as_double((long long)block_select_u64(bits, nullptr, nb, (uint32_t)need, hist));
+    const double lo_cut = t * (1.0 - kEpsTie), tol = kEpsTie * t;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
+        const bool low = bm[i] < lo_cut;
+        const bool near = fabs(bm[i] - t) <= tol;
+        work[i] = near ? 1 : 0;
+        if (low) atomicAdd(&s_cnt, 1u);
+    }
+    __syncthreads();
+    const int64_t take = need - (int64_t)s_cnt;
+    uint64_t kstar = 0;
+    if (take >= 1) kstar = block_select_u64(bkey, work, nb, (uint32_t)take, hist);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
+        const bool low = bm[i] < lo_cut;
+        const bool pick = low || (work[i] && take >= 1 && bkey[i] <= kstar);
+        if (pick) {
+            const uint32_t p = atomicAdd(&ctl->acc_count, 1u);
+            if (p < acc_cap) {
+                acc_key[p] = bkey[i];
+                acc_m[p] = bm[i];
+                acc_flag[p] = 1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Sorting (key, payload index) pairs by key: bitonic sort of 2048-element chunks in LDS,
+// then merge passes in which every element finds its place by binary search in the
+// partner run (keys are distinct).
+constexpr int kSortChunk = 2048;
+
+__global__ __launch_bounds__(1024) void sort_chunk_kernel(const uint64_t* key, uint32_t n, uint64_t* okey,
+                                                          uint32_t* oidx) {
+    __shared__ uint64_t sk[kSortChunk];
+    __shared__ uint32_t si[kSortChunk];
+    const uint32_t base = blockIdx.x * kSortChunk;
+    for (int i = threadIdx.x; i < kSortChunk; i += blockDim.x) {
+        const uint32_t g = base + i;
+        sk[i] = g < n ? key[g] : ~0ull;
+        si[i] = g < n ? g : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    for (int size = 2; size <= kSortChunk; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < kSortChunk / 2; t += blockDim.x) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int jx = i + stride;
+                const bool up = ((i & size) == 0);
+                const uint64_t ki = sk[i], kj = sk[jx];
+                const uint32_t ii = si[i], ij = si[jx];
+                const bool swap = up ? (ki > kj || (ki == kj && ii > ij)) : (ki < kj || (ki == kj && ii < ij));
+                if (swap) {
+                    sk[i] = kj;
+                    sk[jx] = ki;
+                    si[i] = ij;
+                    si[jx] = ii;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < kSortChunk; i += blockDim.x) {
+        const uint32_t g = base + i;
+        if (g < n) {
+            okey[g] = sk[i];
+            oidx[g] = si[i];
+        }
+    }
+}
+
+__global__ void merge_pass_kernel(const uint64_t* ik, const uint32_t* ii, uint32_t n, uint32_t width,
+                                  uint64_t* ok, uint32_t* oi) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const uint32_t pair = g / (2 * width);
+    const uint32_t a0 = pair * 2 * width;
+    const uint32_t b0 = min(a0 + width, n);
+    const uint32_t b1 = min(a0 + 2 * width, n);
+    const uint64_t x = ik[g];
+    uint32_t pos;
+    if (g < b0) {
+        // count of B elements < x
+        uint32_t lo = b0, hi = b1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ik[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        pos = a0 + (g - a0) + (lo - b0);
+    } else {
+        uint32_t lo = a0, hi = b0;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ik[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        pos = a0 + (g - b0) + (lo - a0);
+    }
+    ok[pos] = x;
+    oi[pos] = ii[g];
+}
+
+__global__ void gather_out_kernel(const uint64_t* sk, const uint32_t* si, uint32_t n, const double* m,
+                                  const uint8_t* f, uint64_t* okey, double* om, uint8_t* of) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    okey[g] = sk[g];
+    om[g] = m[si[g]];
+    if (of) of[g] = f[si[g]];
+}
+
+// ---------------------------------------------------------------------------------------
+// Workspace.
+struct WS {
+    Ctl* ctl;
+    uint64_t* cand_key;
+    float* cand_hi;
+    float* cand_lo;
+    float* cand_m;
+    uint64_t* acc_key;
+    double* acc_m;
+    uint8_t* acc_flag;
+    uint64_t* band_key;
+    double* band_m;
+    uint8_t* band_work;
+    uint64_t* sk[2];
+    uint32_t* si[2];
+    uint32_t cand_cap, acc_cap, band_cap;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint32_t band_cap, WS* w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t o_ctl = take(sizeof(Ctl));
+    const size_t o_ck = take(8ull * cand_cap), o_chi = take(4ull * cand_cap), o_clo = take(4ull * cand_cap),
+                 o_cm = take(4ull * cand_cap);
+    const size_t o_ak = take(8ull * acc_cap), o_am = take(8ull * acc_cap), o_af = take(acc_cap);
+    const size_t o_bk = take(8ull * band_cap), o_bm = take(8ull * band_cap), o_bw = take(band_cap);
+    const size_t o_s0 = take(8ull * acc_cap), o_s1 = take(8ull * acc_cap), o_i0 = take(4ull * acc_cap),
+                 o_i1 = take(4ull * acc_cap);
+    if (off > P.ws_bytes) {
+        if (P.ws) hipFree(P.ws);
+        P.ws = nullptr;
+        P.ws_bytes = 0;
+        RR_HIP(hipMalloc(&P.ws, off));
+        P.ws_bytes = off;
+    }
+    char* b = (char*)P.ws;
+    w->ctl = (Ctl*)(b + o_ctl);
+    w->cand_key = (uint64_t*)(b + o_ck);
+    w->cand_hi = (float*)(b + o_chi);
+    w->cand_lo = (float*)(b + o_clo);
+    w->cand_m = (float*)(b + o_cm);
+    w->acc_key = (uint64_t*)(b + o_ak);
+    w->acc_m = (double*)(b + o_am);
+    w->acc_flag = (uint8_t*)(b + o_af);
+    w->band_key = (uint64_t*)(b + o_bk);
+    w->band_m = (double*)(b + o_bm);
+    w->band_work = (uint8_t*)(b + o_bw);
+    w->sk[0] = (uint64_t*)(b + o_s0);
+    w->sk[1] = (uint64_t*)(b + o_s1);
+    w->si[0] = (uint32_t*)(b + o_i0);
+    w->si[1] = (uint32_t*)(b + o_i1);
+    w->cand_cap = cand_cap;
+    w->acc_cap = acc_cap;
+    w->band_cap = band_cap;
+    return RR_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Error bound constants of the FP32 contraction.
+//
+// Model of one MFMA step acc <- acc + sum_e p_e (p_e = w x exact products; at most
+// kMfmaDepth FP32 roundings on the path of any operand, any rounding mode, unit 2^-23) and
+// of the chain of T such steps that forms one output: |G32 - sum(hi + lo)| <=
+// gamma(kMfmaDepth) (T + 1) sum|terms|, plus the representation error of the operands
+// (split: |x - hi - lo| <= 2^-17 |x|; fp32: 2^-24 |x|).
+struct Bound {
+    float two_kappa, csq, gamma_ss, safety;
+};
+constexpr int kMfmaDepth = 2;
+constexpr double kSafety = 4.0;
+
+static double gamma_m(double m, double u = 0x1p-23) { return m * u / (1.0 - m * u); }
+
+Bound bound_constants(const Problem& P, int prec, const std::vector<float>& cabs_host) {
+    const double ks = (double)P.ks;
+    double kappa;
+    if (prec == RR_PREC_SPLIT_BF16) {
+        const double T = 2.0 * ks;                       // hi and lo MFMA per K step
+        kappa = gamma_m(kMfmaDepth) * (T + 1.0) * (1.0 + 0x1p-8) + 0x1p-17;
+    } else {
+        const double T = 8.0 * ks;                       // 8 MFMA (32x32x2) per K step
+        kappa = gamma_m(kMfmaDepth) * (T + 1.0) * (1.0 + 0x1p-23) + 0x1p-24;
+    }
+    double c2 = 0.0;
+    for (float c : cabs_host) c2 += (double)c * (double)c;
+    const int chunks = (int)((P.ncb + draw_cb() - 1) / draw_cb());
+    const double depth_ss = 16.0 * draw_cb() + chunks + 4.0;
+    Bound b;
+    b.two_kappa = (float)(2.0 * kappa * (1.0 + gamma_m(depth_ss)));
+    b.csq = (float)(kappa * kappa * c2 * 1.01);
+    b.gamma_ss = (float)(gamma_m(depth_ss) * 1.01);
+    b.safety = (float)kSafety;
+    return b;
+}
+
+static rr_status cabs_host(const Problem& P, std::vector<float>& out, hipStream_t st) {
+    out.assign((size_t)(32 * P.ncb), 0.f);
+    RR_HIP(hipMemcpyAsync(out.data(), P.cabs, out.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    RR_HIP(hipStreamSynchronize(st));
+    return RR_OK;
+}
+
+static int device_cus(int dev) {
+    static int cached[64] = {};
+    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (dev >= 0 && dev < 64) cached[dev] = cus;
+    return cus;
+}
+
+static DrawArgs make_draw_args(const Problem& P, int prec, const Bound& b) {
+    DrawArgs a{};
+    a.op = prec == RR_PREC_SPLIT_BF16 ? P.op_split : P.op_f32;
+    a.cabs = P.cabs;
+    a.n = (int)P.n;
+    a.n1 = (int)P.n1;
+    a.ks = (int)P.ks;
+    a.ncb = (int)P.ncb;
+    a.scale = (float)P.scale;
+    a.two_kappa = b.two_kappa;
+    a.csq = b.csq;
+    a.gamma_ss = b.gamma_ss;
+    a.safety = b.safety;
+    return a;
+}
+
+static int draw_grid(const Problem& P, uint64_t num) {
+    const uint64_t wave_tiles = (num + draw_tile() - 1) / draw_tile();
+    const uint64_t blocks = (wave_tiles + 3) / 4;
+    const uint64_t cap = (uint64_t)device_cus(P.device) * 2;
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(blocks, cap));
+}
+
+static hipError_t run_select(WS& w, hipStream_t st) {
+    hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(1), 0, st, w.ctl);
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(sel_hist_kernel, dim3(512), dim3(256), 0, st, w.cand_hi, w.cand_lo,
+                           &w.ctl->cand_count, w.ctl, shift);
+        hipLaunchKernelGGL(sel_scan_kernel, dim3(1), dim3(128), 0, st, w.ctl, shift);
+    }
+    return hipGetLastError();
+}
+
+// The draw pipeline shared by Monte Carlo and exact enumeration.
+static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begin, uint64_t N, int mode,
+                               double q_or_a, int prec, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
+                               uint64_t capacity, uint64_t* h_count, hipStream_t st) {
+    auto t_start = std::chrono::steady_clock::now();
+    if (N == 0 || !d_keys || !d_M || !h_count || (mode != RR_MODE_QUANTILE && mode != RR_MODE_THRESHOLD) ||
+        (prec != RR_PREC_SPLIT_BF16 && prec != RR_PREC_FP32)) {
+        set_error("rr_draw: invalid argument");
+        return RR_E_ARG;
+    }
+    uint64_t k = 0;
+    if (mode == RR_MODE_QUANTILE) {
+        if (!(q_or_a > 0.0 && q_or_a <= 1.0)) {
+            set_error("rr_draw: q must be in (0, 1]");
+            return RR_E_ARG;
+        }
+        k = (uint64_t)std::ceil(q_or_a * (double)N * (1.0 - kQFuzz));
+        k = std::min<uint64_t>(std::max<uint64_t>(k, 1), N);
+        if (k > capacity) {
+            *h_count = k;
+            set_error("rr_draw: capacity below the accepted count");
+            return RR_E_CAPACITY;
+        }
+        if (k > (1u << 24)) {
+            set_error("rr_draw: accepted count above 2^24 per call");
+            return RR_E_UNSUPPORTED;
+        }
+    } else if (std::isnan(q_or_a)) {
+        set_error("rr_draw: threshold is NaN");
+        return RR_E_ARG;
+    }
+    const uint64_t chunk0 = std::min<uint64_t>(N, std::max<uint64_t>(1u << 22, 8 * k));
+    const uint64_t chunk = 1ull << 25;
+    const uint32_t cand_cap = (uint32_t)std::max<uint64_t>(chunk0 + (1u << 20), 1u << 23);
+    const uint32_t acc_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(capacity, 1), cand_cap);
+    const uint32_t band_cap = 1u << 20;
+    WS w;
+    rr_status s = ensure_ws(P, cand_cap, acc_cap, band_cap, &w);
+    if (s != RR_OK) return s;
+    std::vector<float> ch;
+    if ((s = cabs_host(P, ch, st)) != RR_OK) return s;
+    const Bound b = bound_constants(P, prec, ch);
+    const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
+    if (exact && !binom) {
+        set_error("rr_draw_exact: binomial table allocation failed");
+        return RR_E_DEVICE;
+    }
+
+    RR_HIP(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), st));
+    {
+        Ctl init{};
+        init.k = (uint32_t)k;
+        init.U = INFINITY;
+        if (mode == RR_MODE_THRESHOLD) {
+            float u = (float)q_or_a;
+            if ((double)u < q_or_a) u = std::nextafter(u, INFINITY);
+            init.U = u;
+        }
+        RR_HIP(hipMemcpyAsync(w.ctl, &init, offsetof(Ctl, hist), hipMemcpyHostToDevice, st));
+    }
+    hipEvent_t e0, e1;
+    RR_HIP(hipEventCreate(&e0));
+    RR_HIP(hipEventCreate(&e1));
+    double draw_ms = 0;
+    int64_t launches = 0;
+    DrawArgs a = make_draw_args(P, prec, b);
+    a.binom = binom;
+    a.seed = seed;
+    a.cand_key = w.cand_key;
+    a.cand_hi = w.cand_hi;
+    a.cand_lo = w.cand_lo;
+    a.cand_m = w.cand_m;
+    a.cand_count = &w.ctl->cand_count;
+    a.cand_cap = cand_cap;
+    uint64_t done = 0;
+    bool first = true;
+    while (done < N) {
+        const uint64_t num = std::min<uint64_t>(N - done, first ? chunk0 : chunk);
+        a.key_begin = key_begin + done;
+        a.num = num;
+        a.U = (mode == RR_MODE_QUANTILE && first) ? nullptr : &w.ctl->U;
+        RR_HIP(hipEventRecord(e0, st));
+        RR_HIP(launch_draw(P.S, prec, exact, false, a, draw_grid(P, num), st));
+        RR_HIP(hipEventRecord(e1, st));
+        ++launches;
+        done += num;
+        first = false;
+        if (mode == RR_MODE_QUANTILE && done < N) {
+            RR_HIP(run_select(w, st));
+            hipLaunchKernelGGL(update_U_kernel, dim3(1), dim3(1), 0, st, w.ctl);
+            RR_HIP(hipGetLastError());
+        }
+        RR_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        RR_HIP(hipEventElapsedTime(&ms, e0, e1));
+        draw_ms += ms;
+    }
+    Ctl hc;
+    RR_HIP(hipMemcpyAsync(&hc, w.ctl, offsetof(Ctl, hist), hipMemcpyDeviceToHost, st));
+    RR_HIP(hipStreamSynchronize(st));
+    if (hc.cand_count > cand_cap) {
+        set_error("rr_draw: candidate buffer overflow (too many draws near the boundary)");
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return RR_E_UNSUPPORTED;
+    }
+    if (mode == RR_MODE_QUANTILE) RR_HIP(run_select(w, st));
+    {
+        const uint32_t nc = hc.cand_count;
+        const int grid = (int)std::max<uint32_t>(1, std::min<uint32_t>((nc + 255) / 256, 4096));
+        hipLaunchKernelGGL(classify_kernel, dim3(grid), dim3(256), 0, st, w.cand_key, w.cand_hi, w.cand_lo,
+                           w.cand_m, w.ctl, mode, q_or_a, w.acc_key, w.acc_m, w.acc_flag, acc_cap, w.band_key,
+                           band_cap);
+        RR_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(cap_band_kernel, dim3(1), dim3(1), 0, st, w.ctl, band_cap);
+    RecheckArgs ra{};
+    ra.X64 = P.X64;
+    ra.keys = w.band_key;
+    ra.count = &w.ctl->band_count;
+    ra.seed = seed;
+    ra.binom = binom;
+    ra.n = (int)P.n;
+    ra.n1 = (int)P.n1;
+    ra.d = (int)P.d;
+    ra.scale = P.scale;
+    ra.out = w.band_m;
+    RR_HIP(launch_recheck(P.S, exact, ra, device_cus(P.device) * 4, st));
+    hipLaunchKernelGGL(band_accept_kernel, dim3(1), dim3(1024), 0, st, w.band_key, w.band_m, w.band_work, w.ctl,
+                       mode, q_or_a, w.acc_key, w.acc_m, w.acc_flag, acc_cap);
+    RR_HIP(hipGetLastError());
+    RR_HIP(hipMemcpyAsync(&hc, w.ctl, offsetof(Ctl, hist), hipMemcpyDeviceToHost, st));
+    RR_HIP(hipStreamSynchronize(st));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (hc.sel_fail || hc.guard_fail) {
+        set_error("rr_draw: selection failed (guard band inconsistent)");
+        return RR_E_DEVICE;
+    }
+    if (hc.overflow) {
+        set_error("rr_draw: guard band larger than the recheck capacity");
+        return RR_E_UNSUPPORTED;
+    }
+    const uint64_t K = hc.acc_count;
+    if (K > capacity) {
+        *h_count = K;
+        set_error("rr_draw: capacity below the accepted count");
+        return RR_E_CAPACITY;
+    }
+    if (mode == RR_MODE_QUANTILE && K != k) {
+        set_error("rr_draw: accepted count differs from k");
+        return RR_E_DEVICE;
+    }
+    if (K > 0) {
+        const uint32_t n = (uint32_t)K;
+        const uint32_t chunks = (n + kSortChunk - 1) / kSortChunk;
+        hipLaunchKernelGGL(sort_chunk_kernel, dim3(chunks), dim3(1024), 0, st, w.acc_key, n, w.sk[0], w.si[0]);
+        int cur = 0;
+        for (uint32_t width = kSortChunk; width < n; width *= 2) {
+            hipLaunchKernelGGL(merge_pass_kernel, dim3((n + 255) / 256), dim3(256), 0, st, w.sk[cur], w.si[cur], n,
+                               width, w.sk[cur ^ 1], w.si[cur ^ 1]);
+            cur ^= 1;
+        }
+        hipLaunchKernelGGL(gather_out_kernel, dim3((n + 255) / 256), dim3(256), 0, st, w.sk[cur], w.si[cur], n,
+                           w.acc_m, w.acc_flag, d_keys, d_M, d_flags);
+        RR_HIP(hipGetLastError());
+        RR_HIP(hipStreamSynchronize(st));
+    }
+    *h_count = K;
+    g_timing.draw_ms = draw_ms;
+    g_timing.launches = launches;
+    g_timing.band = hc.band_count;
+    g_timing.total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return RR_OK;
+}
+
+int pow2_chunks(int n);
+rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_t ldx, int64_t n1,
+                       double ridge_rel, hipStream_t st, rr_problem** out);
+
+}  // namespace rr
+
+using namespace rr;
+
+extern "C" {
+
+const char* rr_last_error(void) { return g_err.c_str(); }
+
+rr_status rr_prepare(const void* d_X, int x_dtype, int64_t n, int64_t d, int64_t ldx, int64_t n1,
+                     double ridge_rel, void* stream, rr_problem** out) {
+    return prepare_impl(d_X, x_dtype, n, d, ldx, n1, ridge_rel, (hipStream_t)stream, out);
+}
+
+void rr_free(rr_problem* p) {
+    if (!p) return;
+    Problem& P = p->P;
+    hipFree(P.X64);
+    hipFree(P.L);
+    hipFree(P.mu);
+    hipFree(P.op_split);
+    hipFree(P.op_f32);
+    hipFree(P.cabs);
+    hipFree(P.ws);
+    delete p;
+}
+
+int64_t rr_problem_n(const rr_problem* p) { return p ? p->P.n : 0; }
+int64_t rr_problem_d(const rr_problem* p) { return p ? p->P.d : 0; }
+int64_t rr_problem_n1(const rr_problem* p) { return p ? p->P.n1 : 0; }
+double rr_problem_lambda(const rr_problem* p) { return p ? p->P.lambda : 0.0; }
+
+rr_status rr_draw_balance(rr_problem* p, uint64_t seed, uint64_t key_begin, uint64_t num_draws, int mode,
+                          double q_or_a, int precision, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
+                          uint64_t capacity, uint64_t* h_count, void* stream) {
+    if (!p) {
+        set_error("rr_draw_balance: null handle");
+        return RR_E_ARG;
+    }
+    if (key_begin + num_draws < key_begin) {
+        set_error("rr_draw_balance: key range wraps");
+        return RR_E_ARG;
+    }
+    return draw_pipeline(p->P, false, seed, key_begin, num_draws, mode, q_or_a, precision, d_keys, d_M, d_flags,
+                         capacity, h_count, (hipStream_t)stream);
+}
+
+rr_status rr_draw_exact(rr_problem* p, int mode, double q_or_a, int precision, uint64_t* d_keys, double* d_M,
+                        uint8_t* d_flags, uint64_t capacity, uint64_t* h_count, void* stream) {
+    if (!p) {
+        set_error("rr_draw_exact: null handle");
+        return RR_E_ARG;
+    }
+    uint64_t total = 0;
+    if (p->P.n > RR_MAX_N_EXACT || !binom_exact(p->P.n, p->P.n1, &total) || total >= (1ull << 40)) {
+        set_error("rr_draw_exact: C(n, n1) too large for enumeration");
+        return RR_E_RANGE;
+    }
+    return draw_pipeline(p->P, true, 0, 0, total, mode, q_or_a, precision, d_keys, d_M, d_flags, capacity, h_count,
+                         (hipStream_t)stream);
+}
+
+rr_status rr_regenerate(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys, uint64_t K,
+                        uint32_t* d_bits, void* stream) {
+    if (!p || (!d_keys && K) || (!d_bits && K)) {
+        set_error("rr_regenerate: invalid argument");
+        return RR_E_ARG;
+    }
+    if (K == 0) return RR_OK;
+    Problem& P = p->P;
+    if (exact && P.n > RR_MAX_N_EXACT) {
+        set_error("rr_regenerate: exact keys need n <= 64");
+        return RR_E_RANGE;
+    }
+    const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
+    const int nw = (int)((P.n + 31) / 32);
+    const int grid = (int)std::min<uint64_t>((K + 3) / 4, (uint64_t)device_cus(P.device) * 8);
+    hipStream_t st = (hipStream_t)stream;
+    RR_HIP(launch_regen(P.S, exact != 0, d_keys, K, seed, (int)P.n, (int)P.n1, binom, d_bits, nw, grid, st));
+    RR_HIP(hipStreamSynchronize(st));
+    return RR_OK;
+}
+
+rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys, uint64_t K,
+                          int precision, float* d_M32, float* d_err, double* d_M64, void* stream) {
+    if (!p || (K && !d_keys) || (precision != RR_PREC_SPLIT_BF16 && precision != RR_PREC_FP32) ||
+        (!d_M32) != (!d_err) || K > 0xFFFFFFFFull) {
+        set_error("rr_balance_keys: invalid argument");
+        return RR_E_ARG;
+    }
+    if (K == 0) return RR_OK;
+    Problem& P = p->P;
+    if (exact && P.n > RR_MAX_N_EXACT) {
+        set_error("rr_balance_keys: exact keys need n <= 64");
+        return RR_E_RANGE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
+    if (d_M32) {
+        std::vector<float> ch;
+        rr_status s = cabs_host(P, ch, st);
+        if (s != RR_OK) return s;
+        const Bound b = bound_constants(P, precision, ch);
+        DrawArgs a = make_draw_args(P, precision, b);
+        a.binom = binom;
+        a.keylist = d_keys;
+        a.seed = seed;
+        a.num = K;
+        a.out_m32 = d_M32;
+        a.out_err = d_err;
+        RR_HIP(launch_draw(P.S, precision, exact != 0, true, a, draw_grid(P, K), st));
+    }
+    if (d_M64) {
+        uint32_t* cnt = nullptr;
+        RR_HIP(hipMalloc(&cnt, sizeof(uint32_t)));
+        const uint32_t k32 = (uint32_t)K;
+        RR_HIP(hipMemcpyAsync(cnt, &k32, sizeof(k32), hipMemcpyHostToDevice, st));
+        RecheckArgs ra{};
+        ra.X64 = P.X64;
+        ra.keys = d_keys;
+        ra.count = cnt;
+        ra.seed = seed;
+        ra.binom = binom;
+        ra.n = (int)P.n;
+        ra.n1 = (int)P.n1;
+        ra.d = (int)P.d;
+        ra.scale = P.scale;
+        ra.out = d_M64;
+        hipError_t e = launch_recheck(P.S, exact != 0, ra, device_cus(P.device) * 4, st);
+        hipError_t e2 = hipStreamSynchronize(st);
+        hipFree(cnt);
+        RR_HIP(e);
+        RR_HIP(e2);
+    }
+    RR_HIP(hipStreamSynchronize(st));
+    return RR_OK;
+}
+
+rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob, const uint64_t* seeds, uint64_t key_begin,
+                                  uint64_t num_draws, int mode, double q_or_a, int precision,
+                                  uint64_t* const* d_keys, double* const* d_M, uint64_t capacity,
+                                  uint64_t* h_counts, void* stream) {
+    if (!P || nprob < 0 || (nprob > 0 && (!seeds || !d_keys || !d_M || !h_counts))) {
+        set_error("rr_draw_balance_batched: invalid argument");
+        return RR_E_ARG;
+    }
+    double total = 0, dk = 0;
+    int64_t launches = 0;
+    uint64_t band = 0;
+    for (int64_t i = 0; i < nprob; ++i) {
+        if (!P[i]) {
+            set_error("rr_draw_balance_batched: null handle");
+            return RR_E_ARG;
+        }
+        rr_status s = draw_pipeline(P[i]->P, false, seeds[i], key_begin, num_draws, mode, q_or_a, precision,
+                                    d_keys[i], d_M[i], nullptr, capacity, &h_counts[i], (hipStream_t)stream);
+        if (s != RR_OK) return s;
+        total += g_timing.total_ms;
+        dk += g_timing.draw_ms;
+        launches += g_timing.launches;
+        band += g_timing.band;
+    }
+    g_timing.total_ms = total;
+    g_timing.draw_ms = dk;
+    g_timing.launches = launches;
+    g_timing.band = band;
+    return RR_OK;
+}
+
+rr_status rr_last_timing(double* total_ms, double* draw_kernel_ms, int64_t* draw_launches, uint64_t* band_size) {
+    if (total_ms) *total_ms = g_timing.total_ms;
+    if (draw_kernel_ms) *draw_kernel_ms = g_timing.draw_ms;
+    if (draw_launches) *draw_launches = g_timing.launches;
+    if (band_size) *band_size = g_timing.band;
+    return RR_OK;
+}
+
+}  // extern "C"

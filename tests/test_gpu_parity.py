@@ -1,0 +1,197 @@
+"""HIP path vs the CPU oracle, through the C ABI (needs an MI355X).
+
+Bar: assignments, accepted key sets and p-value counts bit-exact; M within 1e-9 relative
+where the library reports its FP64 recomputation and 1e-4 relative for FP32 values; the
+FP32 error bound must hold for every draw checked.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import assign, balance, pipeline, prep  # noqa: E402
+from paper_2501_07642_amd import inputs  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_07642_amd as rr
+    rr.load()
+    return rr
+
+
+DEV = "cuda:0"
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def u64(t):
+    return t.cpu().numpy().astype(np.uint64)
+
+
+def keys_t(keys):
+    return dev(np.asarray(keys, dtype=np.uint64).astype(np.int64))
+
+
+@pytest.mark.parametrize("n,n1", [(1, 0), (5, 2), (20, 10), (64, 31), (100, 50), (257, 100), (1000, 500),
+                                  (2000, 1000), (4096, 2048)])
+def test_regenerate_bits_exact(rr, n, n1):
+    if n1 == 0:
+        pytest.skip("n1 must be at least 1")
+    say(f"regenerate n={n} n1={n1}")
+    X = inputs.gaussian_X(n, 3, 1)
+    P = rr.rr_prepare(dev(X), n1, 1e-2)
+    seed = 0xC0FFEE0000000000 + n
+    keys = np.array([0, 1, 2, 77, 2 ** 32 - 1, 2 ** 32, 2 ** 40 + 3, 2 ** 64 - 1], dtype=np.uint64)
+    got = rr.rr_regenerate(P, seed, keys_t(keys)).cpu().numpy().view(np.uint32)
+    want = assign.pack_bits(assign.mc_assignments_batch(seed, keys, n, n1))
+    np.testing.assert_array_equal(got, want)
+
+
+def test_regenerate_exact_ranks(rr):
+    n, n1 = 20, 10
+    say("regenerate exact ranks")
+    P = rr.rr_prepare(dev(inputs.gaussian_X(n, 3, 2)), n1, 0.0)
+    ranks = np.array([0, 1, 2, 1000, 184755, 92377], dtype=np.uint64)
+    got = rr.rr_regenerate(P, 0, keys_t(ranks), exact=True).cpu().numpy().view(np.uint32)
+    want = assign.pack_bits(np.stack([assign.exact_assignment(int(r), n, n1) for r in ranks]))
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("n,n1,d,ridge", [(20, 10, 3, 0.0), (60, 25, 8, 0.0), (100, 50, 100, 1e-2),
+                                          (300, 150, 40, 0.0), (1000, 500, 1000, 1e-2)])
+@pytest.mark.parametrize("prec", ["split", "fp32"])
+def test_balance_values_and_bound(rr, n, n1, d, ridge, prec):
+    say(f"balance n={n} d={d} prec={prec}")
+    X = inputs.gaussian_X(n, d, 3)
+    P = rr.rr_prepare(dev(X), n1, ridge)
+    seed = 99
+    keys = np.arange(5000, 5000 + 256, dtype=np.uint64)
+    pr = rr.PREC_SPLIT_BF16 if prec == "split" else rr.PREC_FP32
+    m32, err, m64 = rr.rr_balance_keys(P, seed, keys_t(keys), pr)
+    m32, err, m64 = m32.cpu().numpy(), err.cpu().numpy(), m64.cpu().numpy()
+    Pr = prep.prepare(X, n1, ridge)
+    W = assign.mc_assignments_batch(seed, keys, n, n1)
+    want = balance.mahalanobis_batch(X, W, Pr["S_lam"])
+    np.testing.assert_allclose(m64, want, rtol=1e-9)
+    np.testing.assert_allclose(m32, want, rtol=1e-4, atol=1e-4 * d * 1e-3)
+    assert np.all(np.abs(m32.astype(np.float64) - m64) <= err)
+    say(f"  max |m32-m64|/err = {np.max(np.abs(m32 - m64) / err):.3e}, err/M = {np.median(err / m64):.2e}")
+
+
+def _check_pool(rr, X, n1, ridge, seed, N, mode, qa, prec):
+    P = rr.rr_prepare(dev(X), n1, ridge)
+    pr = rr.PREC_SPLIT_BF16 if prec == "split" else rr.PREC_FP32
+    md = rr.MODE_QUANTILE if mode == "quantile" else rr.MODE_THRESHOLD
+    keys, M, flags = rr.rr_draw_balance(P, seed, 0, N, md, qa, pr)
+    acc, Macc, Mall = pipeline.draw_balance(X, n1, ridge, seed, 0, N, mode, qa)
+    got = u64(keys)
+    np.testing.assert_array_equal(got, acc)
+    Mg, fl = M.cpu().numpy(), flags.cpu().numpy().astype(bool)
+    np.testing.assert_allclose(Mg[fl], Macc[fl], rtol=1e-9)
+    np.testing.assert_allclose(Mg[~fl], Macc[~fl], rtol=1e-4)
+    return P, got, rr.rr_last_timing()
+
+
+@pytest.mark.parametrize("prec", ["split", "fp32"])
+@pytest.mark.parametrize("mode,qa", [("quantile", 0.05), ("quantile", 1e-3), ("threshold", 4.0)])
+def test_pool_small(rr, prec, mode, qa):
+    say(f"pool small {mode} {qa} {prec}")
+    X = inputs.gaussian_X(60, 8, 5)
+    _, got, t = _check_pool(rr, X, 30, 0.0, 4242, 4000, mode, qa, prec)
+    say(f"  accepted {len(got)} band {t['band']}")
+
+
+def test_pool_ragged_tiles(rr):
+    # draw counts that leave partial tiles; n not a multiple of 16 / 32 / 64
+    for n, d, N in [(37, 5, 1), (37, 5, 63), (101, 33, 129), (531, 70, 1000)]:
+        say(f"pool ragged n={n} d={d} N={N}")
+        X = inputs.gaussian_X(n, d, n)
+        _check_pool(rr, X, n // 3, 1e-3, 7, N, "quantile", 0.1, "split")
+
+
+def test_exact_enumeration_c1(rr):
+    w = inputs.WORKLOADS["exact_n20_d3"]
+    say("exact enumeration n=20")
+    X = inputs.workload_X("exact_n20_d3")
+    P = rr.rr_prepare(dev(X), w["n1"], 0.0)
+    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32):
+        keys, M, flags = rr.rr_draw_exact(P, rr.MODE_QUANTILE, w["q"], prec)
+        acc, Macc, _ = pipeline.draw_exact(X, w["n1"], 0.0, "quantile", w["q"])
+        assert len(acc) == 1848
+        np.testing.assert_array_equal(u64(keys), acc)
+
+
+def test_mc_c2_and_frt(rr):
+    name = "mc_n100_d100"
+    w = inputs.WORKLOADS[name]
+    say("C2 pool + FRT")
+    X = inputs.workload_X(name)
+    P, acc, t = _check_pool(rr, X, w["n1"], w["ridge_rel"], w["seed"], w["num_draws"], "quantile", w["q"],
+                            "fp32")
+    assert len(acc) == 2000
+    obs = inputs.obs_pick(len(acc), w["obs_seed"])
+    wo = pipeline.regenerate(w["seed"], acc[obs:obs + 1], w["n"], w["n1"])[0]
+    Y = inputs.outcomes(X, wo, w["tau"], w["noise_sd"], w["y_seed"])
+    counts, tau_hat = rr.rr_rand_test(P, w["seed"], keys_t(acc), obs, dev(Y), w["taus"])
+    ref = pipeline.rand_test_keys(w["seed"], acc, w["n"], w["n1"], obs, Y, w["taus"])
+    assert counts.cpu().tolist() == ref["counts"]
+    assert abs(tau_hat - ref["tau_hat"]) <= 1e-12 * max(1.0, abs(ref["tau_hat"]))
+    assert min(ref["counts"]) >= 1
+
+
+def test_rand_test_exact_c1(rr):
+    name = "exact_n20_d3"
+    w = inputs.WORKLOADS[name]
+    say("C1 FRT")
+    X = inputs.workload_X(name)
+    P = rr.rr_prepare(dev(X), w["n1"], 0.0)
+    keys, _, _ = rr.rr_draw_exact(P, rr.MODE_QUANTILE, w["q"], rr.PREC_SPLIT_BF16)
+    acc = u64(keys)
+    obs = inputs.obs_pick(len(acc), w["obs_seed"])
+    wo = pipeline.regenerate(0, acc[obs:obs + 1], w["n"], w["n1"], exact=True)[0]
+    Y = inputs.outcomes(X, wo, w["tau"], w["noise_sd"], w["y_seed"])
+    counts, _ = rr.rr_rand_test(P, 0, keys, obs, dev(Y), w["taus"], exact=True)
+    ref = pipeline.rand_test_keys(0, acc, w["n"], w["n1"], obs, Y, w["taus"], exact=True)
+    assert counts.cpu().tolist() == ref["counts"]
+
+
+def test_errors(rr):
+    say("error paths")
+    X = inputs.gaussian_X(10, 12, 1)
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_prepare(dev(X), 5, 0.0)
+    assert e.value.status == "RR_E_SINGULAR"
+    P = rr.rr_prepare(dev(X), 5, 1e-2)
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_draw_balance(P, 1, 0, 1000, rr.MODE_QUANTILE, 0.1, rr.PREC_SPLIT_BF16, capacity=50)
+    assert e.value.status == "RR_E_CAPACITY" and e.value.count == 100
+    keys, _, _ = rr.rr_draw_balance(P, 1, 0, 1000, rr.MODE_QUANTILE, 0.1, rr.PREC_SPLIT_BF16)
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_rand_test(P, 1, keys, 100, dev(np.ones(10)), [0.0])
+    assert e.value.status == "RR_E_OBS"
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_rand_test(P, 1, keys, 0, dev(np.ones(10)), [1e-30])
+    assert e.value.status == "RR_E_RANGE"
+    P2 = rr.rr_prepare(dev(inputs.gaussian_X(70, 3, 1)), 35, 0.0)
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_draw_exact(P2, rr.MODE_QUANTILE, 0.1, rr.PREC_SPLIT_BF16)
+    assert e.value.status == "RR_E_RANGE"
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_draw_balance(P, 1, 0, 1000, rr.MODE_QUANTILE, 0.0, rr.PREC_SPLIT_BF16)
+    assert e.value.status == "RR_E_ARG"
