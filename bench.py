@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""Benchmark of the rerandomization hot path on one MI355X.
+
+Metric: balance-checked draws per second at n = d = 1000 (BF16 hi+lo MFMA form, with the
+plain FP32 form run on the same workload and its accepted set compared).  One step is one
+pass of the whole path over one synthetic problem: rr_prepare (whitening), rr_draw_balance
+(generate, contract, accept, key-only output) and rr_rand_test (201-point null grid).
+
+Workload (default): n = 1000, n1 = 500, d = 1000 iid N(0, 1) covariates, ridge 1e-2,
+1e8 Philox draws, q = 1.2e-5 (1200 accepted).  Inputs are resident in HBM before timing.
+
+Prints one JSON line.  --gpus above 1 exits with an error: this path runs on one GPU.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "balance-checked draws/sec at n=d=1000: BF16-split MFMA vs FP32, same accept set"
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
+PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 (matrix / vector)
+
+
+def cpu_baseline(X, w, sample):
+    """The oracle, as it stands, on the first `sample` draws of the workload."""
+    import numpy as np
+    from oracle import accept, pipeline
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = len(os.sched_getaffinity(0))
+    keys = np.arange(sample, dtype=np.uint64)
+    t0 = time.perf_counter()
+    M = pipeline.balance_of_keys(X, w["n1"], w["ridge_rel"], w["seed"], keys)
+    accept.accept_quantile(keys, M, accept.quantile_count(w["q"], sample))
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "draws/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"first {sample} draw keys of the workload: Philox draws, n1-of-n selection, "
+                      f"FP64 textbook M, q-quantile acceptance over the sample ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="stream_n1000_d1000")
+    ap.add_argument("--draws", type=int, default=None, help="override the draw count (not the benchmark)")
+    ap.add_argument("--cpu-sample", type=int, default=30000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this hot path runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2501_07642_amd as rr
+    from paper_2501_07642_amd import inputs
+
+    w = dict(inputs.WORKLOADS[args.workload])
+    if args.draws:
+        w["num_draws"] = args.draws
+    n, n1, d, N, q = w["n"], w["n1"], w["d"], w["num_draws"], w["q"]
+    dev = torch.device("cuda:0")
+    X = inputs.workload_X(args.workload)
+    Xd = torch.from_numpy(X).to(dev)
+    taus = w["taus"]
+
+    def step(Yd, obs):
+        P = rr.rr_prepare(Xd, n1, w["ridge_rel"])
+        keys, M, flags = rr.rr_draw_balance(P, w["seed"], w["key_begin"], N, rr.MODE_QUANTILE, q,
+                                            rr.PREC_SPLIT_BF16)
+        t = rr.rr_last_timing()
+        counts = None
+        if Yd is not None:
+            counts, _ = rr.rr_rand_test(P, w["seed"], keys, obs, Yd, taus)
+        return P, keys, t, counts
+
+    # first pass builds the outcome vector from an accepted assignment (product output)
+    P, keys, _, _ = step(None, 0)
+    obs = inputs.obs_pick(len(keys), w["obs_seed"])
+    bits = rr.rr_regenerate(P, w["seed"], keys[obs:obs + 1]).cpu().numpy().view(np.uint32)
+    wo = ((bits[0][np.arange(n) // 32] >> (np.arange(n) % 32)) & 1).astype(np.float64)
+    Yd = torch.from_numpy(inputs.outcomes(X, wo, w["tau"], w["noise_sd"], w["y_seed"])).to(dev)
+    del P
+    for _ in range(args.warmup):
+        step(Yd, obs)
+    torch.cuda.synchronize()
+    draw_ms = 0.0
+    launches = 0
+    band = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        P, keys_s, t, counts = step(Yd, obs)
+        draw_ms += t["draw_kernel_ms"]
+        launches += t["draw_launches"]
+        band = t["band"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = N / (ms_per_step / 1000.0)
+    keys_split = keys_s.cpu().numpy()
+
+    flops_per_draw = 4.0 * n * d            # hi and lo products of the dense W X~ contraction
+    avg_launch_ms = draw_ms / max(launches, 1)
+    achieved = flops_per_draw * N * args.steps / (draw_ms / 1000.0) / 1e12
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                "kernel": "draw_kernel (Philox select + BF16 hi/lo MFMA + reduce + prefilter)",
+                "avg_launch_ms": avg_launch_ms, "launches_per_step": launches / args.steps,
+                "algorithmic_flops_per_draw": flops_per_draw}
+
+    fp32 = None
+    if not args.no_fp32:
+        P = rr.rr_prepare(Xd, n1, w["ridge_rel"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        keys32, _, _ = rr.rr_draw_balance(P, w["seed"], w["key_begin"], N, rr.MODE_QUANTILE, q, rr.PREC_FP32)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        t = rr.rr_last_timing()
+        same = bool(np.array_equal(keys32.cpu().numpy(), keys_split))
+        a32 = 2.0 * n * d * N / (t["draw_kernel_ms"] / 1000.0) / 1e12
+        fp32 = {"draws_per_s": N / dt, "draw_kernel_ms": t["draw_kernel_ms"], "same_accept_set": same,
+                "mfma_tflops": a32, "frac_fp32_peak": a32 / PEAK_FP32_TFLOPS,
+                "split_speedup": (N / dt) and value / (N / dt)}
+
+    base = None
+    if not args.no_cpu_baseline:
+        base = cpu_baseline(X, w, args.cpu_sample)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "draws/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "n1": n1, "d": d, "num_draws": N, "q": q,
+                   "accepted": int(len(keys_split)), "ridge_rel": w["ridge_rel"], "precision": "split_bf16",
+                   "step": "rr_prepare + rr_draw_balance + rr_rand_test(201 nulls)"},
+        "roofline": roofline, "cpu_baseline": base, "fp32_form": fp32,
+        "draw_kernel_ms_per_step": draw_ms / args.steps, "guard_band": band,
+        "rand_test_counts_min": int(counts.min().item()) if counts is not None else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -134,8 +134,16 @@ __global__ __launch_bounds__(256) void draw_kernel(DrawArgs a) {
                         }
                     }
                 } else {
+                    // FP32 form: each K step starts from a zero accumulator and is added to
+                    // the running total on the VALU, so the rounding chain of an output is
+                    // 16 steps inside the K step plus one add per K step.
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb) {
+                        f32x16 st[DB];
+#pragma unroll
+                        for (int db = 0; db < DB; ++db)
+#pragma unroll
+                            for (int e = 0; e < 16; ++e) st[db][e] = 0.f;
 #pragma unroll
                         for (int p = 0; p < 2; ++p) {
                             const uint4 av = rec[cb * kRecordU4 + 64 * p + lane];
@@ -146,10 +154,12 @@ __global__ __launch_bounds__(256) void draw_kernel(DrawArgs a) {
 #pragma unroll
                                 for (int db = 0; db < DB; ++db) {
                                     const float bv = (float)((byte2[db] >> (8 * p + 2 * q + h)) & 1u);
-                                    acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], bv, acc[cb][db], 0, 0, 0);
+                                    st[db] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], bv, st[db], 0, 0, 0);
                                 }
                             }
                         }
+#pragma unroll
+                        for (int db = 0; db < DB; ++db) acc[cb][db] += st[db];
                     }
                 }
             }
@@ -217,67 +227,95 @@ __global__ __launch_bounds__(256) void draw_kernel(DrawArgs a) {
 }
 
 // ---------------------------------------------------------------------------------------
-// FP64 recomputation: one workgroup per listed draw.  Wave 0 regenerates the treated set,
-// then threads sum whitened rows over treated units in ascending unit order for their
-// covariates, and the squares are reduced in a fixed tree.
+// FP64 recomputation of M for listed draws: 16 draws per workgroup.  The four waves
+// regenerate the treated sets into LDS; each thread then owns up to four covariates of a
+// 1024-column group and adds the whitened rows of treated units in ascending unit order
+// (row reads are coalesced and shared by the 16 draws); ||G||^2 is reduced per draw in a
+// fixed order.
+constexpr int kRecheckTile = 16;
 
 template <int S, bool EXACT>
 __global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a) {
-    __shared__ uint32_t bits[8 * kMaxS];
-    __shared__ uint32_t hist[256];
-    __shared__ uint2 list[64];
-    __shared__ uint16_t units[RR_MAX_N];
-    __shared__ double red[256];
-    __shared__ int nt;
-    const int tid = threadIdx.x;
+    constexpr int WS = 8 * S + 1;
+    __shared__ uint32_t bits[kRecheckTile][WS];
+    __shared__ uint32_t hist[4][256];
+    __shared__ uint2 list[4][64];
+    __shared__ double red[4][kRecheckTile];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint32_t cnt = *a.count;
-    for (uint32_t e = blockIdx.x; e < cnt; e += gridDim.x) {
-        const uint64_t key = a.keys[e];
-        if (tid < 64) {
-            if constexpr (EXACT) {
-                if (tid == 0) {
-                    const uint64_t m = colex_unrank_mask(key, a.n, a.n1, a.binom);
-                    bits[0] = (uint32_t)m;
-                    bits[1] = (uint32_t)(m >> 32);
+    for (uint32_t e0 = blockIdx.x * kRecheckTile; e0 < cnt; e0 += gridDim.x * kRecheckTile) {
+        const int nt = (int)min<uint32_t>(kRecheckTile, cnt - e0);
+        for (int t = wave; t < kRecheckTile; t += 4) {
+            if (t < nt) {
+                if constexpr (EXACT) {
+                    if (lane == 0) {
+                        const uint64_t m = colex_unrank_mask(a.keys[e0 + t], a.n, a.n1, a.binom);
+                        for (int w = 0; w < 8 * S; ++w) bits[t][w] = 0u;
+                        bits[t][0] = (uint32_t)m;
+                        bits[t][1] = (uint32_t)(m >> 32);
+                    }
+                } else {
+                    gen_mc_bits<S>(a.seed, a.keys[e0 + t], a.n, a.n1, hist[wave], list[wave], bits[t]);
                 }
             } else {
-                gen_mc_bits<S>(a.seed, key, a.n, a.n1, hist, list, bits);
+                for (int w = lane; w < 8 * S; w += 64) bits[t][w] = 0u;
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
-        if (tid == 0) {
-            int c = 0;
-            for (int i = 0; i < a.n; ++i)
-                if ((bits[i >> 5] >> (i & 31)) & 1u) units[c++] = (uint16_t)i;
-            nt = c;
+        double part[kRecheckTile];
+#pragma unroll
+        for (int t = 0; t < kRecheckTile; ++t) part[t] = 0.0;
+        for (int cg = 0; cg < a.d; cg += 1024) {
+            double G[kRecheckTile][4];
+#pragma unroll
+            for (int t = 0; t < kRecheckTile; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) G[t][c] = 0.0;
+            for (int i = 0; i < a.n; ++i) {
+                double x[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int col = cg + tid + 256 * c;
+                    x[c] = col < a.d ? a.X64[(size_t)i * a.d + col] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < kRecheckTile; ++t) {
+                    const uint32_t w = __builtin_amdgcn_readfirstlane(bits[t][i >> 5]);
+                    if ((w >> (i & 31)) & 1u) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) G[t][c] += x[c];
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kRecheckTile; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) part[t] = fma(G[t][c], G[t][c], part[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < kRecheckTile; ++t) {
+            const double v = wave_sum<double>(part[t]);
+            if (lane == 0) red[wave][t] = v;
         }
         __syncthreads();
-        double part = 0.0;
-        for (int col = tid; col < a.d; col += 256) {
-            double g = 0.0;
-            for (int t = 0; t < nt; ++t) g += a.X64[(size_t)units[t] * a.d + col];
-            part += g * g;
-        }
-        red[tid] = part;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o) red[tid] += red[tid + o];
-            __syncthreads();
-        }
-        if (tid == 0) a.out[e] = a.scale * red[0];
+        if (tid < nt) a.out[e0 + tid] = a.scale * ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------------------
 // Host-side launchers.
-constexpr int kCB = 4, kDB = 2;
+constexpr int kDB = 2;
+// covariate blocks per chunk: the FP32 form keeps a second accumulator set per K step
+constexpr int cb_for(int prec) { return prec == RR_PREC_SPLIT_BF16 ? 4 : 2; }
 
 size_t draw_lds_bytes(int S) { return 4 * ((32 * kDB) * (8 * S + 1) + 256 + 128) * sizeof(uint32_t); }
 
 template <int S, int PREC, int GEN>
 static hipError_t launch_draw_t(const DrawArgs& a, int grid, hipStream_t st) {
-    auto k = draw_kernel<S, PREC, GEN, kCB, kDB>;
+    auto k = draw_kernel<S, PREC, GEN, cb_for(PREC), kDB>;
     const size_t lds = draw_lds_bytes(S);
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -321,9 +359,10 @@ hipError_t launch_draw(int S, int prec, bool exact, bool from_list, const DrawAr
 }
 
 int draw_tile() { return 32 * kDB; }
-int draw_cb() { return kCB; }
+int draw_cb(int prec) { return cb_for(prec); }
 
 hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hipStream_t st) {
+    grid = std::max(1, grid);
     if (exact) {
         hipLaunchKernelGGL((recheck_kernel<1, true>), dim3(grid), dim3(256), 0, st, a);
     } else {

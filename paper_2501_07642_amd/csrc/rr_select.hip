@@ -29,7 +29,7 @@ hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hip
 hipError_t launch_regen(int S, bool exact, const uint64_t* keys, uint64_t K, uint64_t seed, int n, int n1,
                         const uint64_t* binom, uint32_t* out, int nw, int grid, hipStream_t st);
 int draw_tile();
-int draw_cb();
+int draw_cb(int prec);
 
 
 constexpr double kEpsTie = 1e-10;
@@ -459,35 +459,40 @@ static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint
 // ---------------------------------------------------------------------------------------
 // Error bound constants of the FP32 contraction.
 //
-// Model of one MFMA step acc <- acc + sum_e p_e (p_e = w x exact products; at most
-// kMfmaDepth FP32 roundings on the path of any operand, any rounding mode, unit 2^-23) and
-// of the chain of T such steps that forms one output: |G32 - sum(hi + lo)| <=
-// gamma(kMfmaDepth) (T + 1) sum|terms|, plus the representation error of the operands
-// (split: |x - hi - lo| <= 2^-17 |x|; fp32: 2^-24 |x|).
+// Rounding model of the gfx950 MFMA, checked on the device: a 32x32x16 BF16 MFMA adds the
+// products of each half of its K range to the accumulator with one round-to-nearest-even
+// step (products exact, the 8-product sums exact or at worst rounded in FP32); a 32x32x2
+// FP32 MFMA adds its two products one at a time.  Each rounding step errs by at most
+// u |partial sum| <= u sum|terms| (u = 2^-24), so for one output
+//   split: |G32 - sum(hi + lo)| <= (gamma(4 ks) + gamma(7)) sum(|hi| + |lo|)
+//          (2 MFMA per K step, 2 rounding steps each), and |x - hi - lo| <= 2^-18 |x|;
+//   fp32:  K steps start from zero (16 rounding steps inside a step) and are summed on the
+//          VALU (ks steps): gamma(16 + ks) sum|x32|, and |x - x32| <= 2^-24 |x|.
+// Hence |G32_j - G_j| <= kappa cabs_j with cabs_j = sum_i |X~_ij| >= the treated sum.  M32
+// errs by at most scale (2 kappa sum_j |G32_j| cabs_j + kappa^2 sum_j cabs_j^2) plus the
+// FP32 sum of squares (gamma(depth) M32); the assembled bound is multiplied by kSafety.
 struct Bound {
     float two_kappa, csq, gamma_ss, safety;
 };
-constexpr int kMfmaDepth = 2;
-constexpr double kSafety = 4.0;
+constexpr double kU = 0x1p-24;
+constexpr double kSafety = 1.25;
 
-static double gamma_m(double m, double u = 0x1p-23) { return m * u / (1.0 - m * u); }
+static double gamma_m(double m) { return m * kU / (1.0 - m * kU); }
 
 Bound bound_constants(const Problem& P, int prec, const std::vector<float>& cabs_host) {
     const double ks = (double)P.ks;
     double kappa;
-    if (prec == RR_PREC_SPLIT_BF16) {
-        const double T = 2.0 * ks;                       // hi and lo MFMA per K step
-        kappa = gamma_m(kMfmaDepth) * (T + 1.0) * (1.0 + 0x1p-8) + 0x1p-17;
-    } else {
-        const double T = 8.0 * ks;                       // 8 MFMA (32x32x2) per K step
-        kappa = gamma_m(kMfmaDepth) * (T + 1.0) * (1.0 + 0x1p-23) + 0x1p-24;
-    }
+    if (prec == RR_PREC_SPLIT_BF16)
+        kappa = (gamma_m(4.0 * ks) + gamma_m(7.0)) * (1.0 + 0x1p-8 + 0x1p-16) + 1.05 * 0x1p-18;
+    else
+        kappa = gamma_m(16.0 + ks) * (1.0 + 0x1p-23) + 0x1p-24;
     double c2 = 0.0;
     for (float c : cabs_host) c2 += (double)c * (double)c;
-    const int chunks = (int)((P.ncb + draw_cb() - 1) / draw_cb());
-    const double depth_ss = 16.0 * draw_cb() + chunks + 4.0;
+    const int cb = draw_cb(prec);
+    const int chunks = (int)((P.ncb + cb - 1) / cb);
+    const double depth_ss = 16.0 * cb + chunks + 4.0;
     Bound b;
-    b.two_kappa = (float)(2.0 * kappa * (1.0 + gamma_m(depth_ss)));
+    b.two_kappa = (float)(2.0 * kappa * (1.0 + gamma_m(depth_ss)) * (1.0 + 1e-6));
     b.csq = (float)(kappa * kappa * c2 * 1.01);
     b.gamma_ss = (float)(gamma_m(depth_ss) * 1.01);
     b.safety = (float)kSafety;
@@ -670,7 +675,7 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
     ra.d = (int)P.d;
     ra.scale = P.scale;
     ra.out = w.band_m;
-    RR_HIP(launch_recheck(P.S, exact, ra, device_cus(P.device) * 4, st));
+    RR_HIP(launch_recheck(P.S, exact, ra, (int)std::min<uint64_t>((hc.cand_count + 15) / 16 + 1, (uint64_t)device_cus(P.device) * 2), st));
     hipLaunchKernelGGL(band_accept_kernel, dim3(1), dim3(1024), 0, st, w.band_key, w.band_m, w.band_work, w.ctl,
                        mode, q_or_a, w.acc_key, w.acc_m, w.acc_flag, acc_cap);
     RR_HIP(hipGetLastError());
@@ -851,7 +856,7 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
         ra.d = (int)P.d;
         ra.scale = P.scale;
         ra.out = d_M64;
-        hipError_t e = launch_recheck(P.S, exact != 0, ra, device_cus(P.device) * 4, st);
+        hipError_t e = launch_recheck(P.S, exact != 0, ra, (int)std::min<uint64_t>((K + 15) / 16, (uint64_t)device_cus(P.device) * 2), st);
         hipError_t e2 = hipStreamSynchronize(st);
         hipFree(cnt);
         RR_HIP(e);
