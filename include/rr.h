@@ -185,10 +185,12 @@ rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob, const uin
                                   void* stream);
 
 /* Timing of the last rr_draw_balance / rr_draw_exact / rr_draw_balance_batched call on
- * this thread, measured with HIP events on its stream: total milliseconds and the
- * milliseconds spent in the fused generate-and-contract kernel; number of its launches. */
-rr_status rr_last_timing(double* total_ms, double* draw_kernel_ms, int64_t* draw_launches,
-                         uint64_t* band_size);
+ * this thread: host wall milliseconds of the call, and HIP-event milliseconds summed over the
+ * launches of the contraction kernel (on the caller's stream) and of the generation kernel
+ * (on the handle's internal stream, overlapping the contraction); number of chunks (launches
+ * of each kernel); size of the FP64-rechecked guard band.  All pointers may be null. */
+rr_status rr_last_timing(double* total_ms, double* contract_ms, double* gen_ms,
+                         int64_t* draw_launches, uint64_t* band_size);
 
 #ifdef __cplusplus
 }

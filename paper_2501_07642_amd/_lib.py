@@ -28,7 +28,7 @@ SIGNATURES = [
     ("rr_balance_keys", _I, [_P, _U64, _I, _P, _U64, _I, _P, _P, _P, _P]),
     ("rr_rand_test", _I, [_P, _U64, _I, _P, _U64, _U64, _P, _P, _I64, _P, C.POINTER(_D), _P]),
     ("rr_draw_balance_batched", _I, [_P, _I64, _P, _U64, _U64, _I, _D, _I, _P, _P, _U64, _P, _P]),
-    ("rr_last_timing", _I, [C.POINTER(_D), C.POINTER(_D), C.POINTER(_I64), C.POINTER(_U64)]),
+    ("rr_last_timing", _I, [C.POINTER(_D), C.POINTER(_D), C.POINTER(_D), C.POINTER(_I64), C.POINTER(_U64)]),
 ]
 
 _lib = None
@@ -229,6 +229,6 @@ def rr_draw_balance_batched(problems, seeds, key_begin, num_draws, mode=MODE_QUA
 
 
 def rr_last_timing():
-    t, dk, nl, band = C.c_double(), C.c_double(), C.c_int64(), C.c_uint64()
-    _check(load().rr_last_timing(C.byref(t), C.byref(dk), C.byref(nl), C.byref(band)))
-    return dict(total_ms=t.value, draw_kernel_ms=dk.value, draw_launches=nl.value, band=band.value)
+    t, ck, gk, nl, band = C.c_double(), C.c_double(), C.c_double(), C.c_int64(), C.c_uint64()
+    _check(load().rr_last_timing(C.byref(t), C.byref(ck), C.byref(gk), C.byref(nl), C.byref(band)))
+    return dict(total_ms=t.value, contract_ms=ck.value, gen_ms=gk.value, launches=nl.value, band=band.value)

@@ -1,0 +1,258 @@
+// Balance contraction: M for every candidate draw from its bitmask, on MFMA.
+//
+// Method (section 2.2, Appendix A remark): with X~ = (X - 1 mu^T) L^-T the centred,
+// whitened covariates, the treated sum G = sum_{i in T} X~_i = W X~ (W the 0/1 row of the
+// draw) gives M = n / (n1 n0) ||G||^2 (chi^2_d scale).  Centring makes the control sum
+// redundant: sum_{i in C} X~_i = -G.
+//
+// One workgroup (4 waves) takes a tile of 128 DB draws; wave w owns draws
+// [32 DB w, 32 DB (w+1)).  G^T = X~^T W^T is computed per covariate chunk of 32 CB: the A
+// operand (32 covariates x 16 units of X~^T) comes from the precomputed operand records,
+// staged through LDS two K steps at a time (double-buffered, shared by the four waves);
+// the B operand (16 units x 32 draws of W^T) is expanded from the tile's bitmasks in LDS.
+// In an output block, lane l holds draw l % 32 and 16 covariates, so ||G||^2 and the error
+// bound are reduced in registers and across the two lane halves.
+//
+//   split BF16: X~ = hi + lo, two 32x32x16 BF16 MFMA per K step into one FP32 accumulator;
+//   FP32:       32x32x2 FP32 MFMA; each K step starts from zero and is added on the VALU.
+#include <algorithm>
+
+#include "rr_internal.h"
+
+namespace rr {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+
+constexpr int kKStage = 2;   // K steps per LDS stage
+
+__device__ __forceinline__ uint4 expand_bf16(uint32_t x) {
+    // 8 bits -> 8 BF16 values (1.0 = 0x3F80 or 0): bit 2k -> low half of dword k,
+    // bit 2k+1 -> high half.  y holds bit i at i and at i + 15.
+    const uint32_t y = x | (x << 15);
+    uint4 r;
+    r.x = __umul24(y & 0x00010001u, 0x3F80u);
+    r.y = __umul24(y & 0x00040004u, 0x3F80u >> 2);
+    r.z = __umul24(y & 0x00100010u, 0x3F80u >> 4);
+    r.w = __umul24(y & 0x00400040u, 0x3F80u >> 6);
+    return r;
+}
+
+template <int PREC, int CB, int DB, int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void contract_kernel(ContractArgs a) {
+    constexpr int TILE = 4 * 32 * DB;
+    constexpr int WSTR = 8 * S + 1;                       // +1: 32 draws hit 32 banks
+    constexpr int STAGE_U4 = kKStage * CB * kRecordU4;    // uint4 per stage
+    constexpr int PER_THREAD = STAGE_U4 / 256;
+    extern __shared__ uint4 smem4[];
+    uint4* sA = smem4;                                     // [2][kKStage][CB][128]
+    uint32_t* sbits = reinterpret_cast<uint32_t*>(smem4 + 2 * STAGE_U4);   // [TILE][WSTR]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int h = lane >> 5, j = lane & 31;
+    const int nchunks = a.ncb / CB;
+    const int nst = (a.ks + kKStage - 1) / kKStage;
+    const int total = nchunks * nst;
+    const uint64_t ntiles = (a.num + TILE - 1) / TILE;
+
+    auto load_stage = [&](int gs, uint4* r) {
+        const int chunk = gs / nst, kst = gs % nst;
+#pragma unroll
+        for (int q = 0; q < PER_THREAD; ++q) {
+            const int e = tid + 256 * q;
+            const int kk = e / (CB * kRecordU4), rem = e % (CB * kRecordU4);
+            const int cb = rem / kRecordU4, w = rem % kRecordU4;
+            const int k = kst * kKStage + kk;
+            r[q] = k < a.ks ? a.op[((size_t)k * a.ncb + chunk * CB + cb) * kRecordU4 + w] : make_uint4(0, 0, 0, 0);
+        }
+    };
+
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint64_t tile0 = t * TILE;
+        for (int e = tid; e < TILE * 8 * S; e += 256) {
+            const int dr = e / (8 * S), w = e % (8 * S);
+            const uint64_t idx = tile0 + dr;
+            sbits[dr * WSTR + w] = idx < a.num ? a.bits[idx * (8 * S) + w] : 0u;
+        }
+        uint4 pre[PER_THREAD];
+        load_stage(0, pre);
+#pragma unroll
+        for (int q = 0; q < PER_THREAD; ++q) sA[tid + 256 * q] = pre[q];
+        __syncthreads();
+
+        float ss[DB], sa[DB];
+#pragma unroll
+        for (int db = 0; db < DB; ++db) ss[db] = sa[db] = 0.f;
+        f32x16 acc[CB][DB];
+        const uint32_t* myb = sbits + (wave * 32 * DB + j) * WSTR;
+
+        for (int gs = 0; gs < total; ++gs) {
+            const int chunk = gs / nst, kst = gs % nst;
+            if (kst == 0) {
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int db = 0; db < DB; ++db)
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) acc[cb][db][e] = 0.f;
+            }
+            if (gs + 1 < total) load_stage(gs + 1, pre);
+            const uint4* st = sA + (gs & 1) * STAGE_U4;
+            uint32_t word[DB];
+#pragma unroll
+            for (int db = 0; db < DB; ++db) word[db] = myb[32 * db * WSTR + kst];   // units 32 kst .. +31
+#pragma unroll
+            for (int kk = 0; kk < kKStage; ++kk) {
+                if (kst * kKStage + kk < a.ks) {
+                    const uint4* rec = st + kk * CB * kRecordU4;
+                    if constexpr (PREC == RR_PREC_SPLIT_BF16) {
+                        bf16x8 bw[DB];
+#pragma unroll
+                        for (int db = 0; db < DB; ++db)
+                            bw[db] = __builtin_bit_cast(bf16x8, expand_bf16((word[db] >> (16 * kk + 8 * h)) & 0xFFu));
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) {
+                            const bf16x8 ahi = __builtin_bit_cast(bf16x8, rec[cb * kRecordU4 + lane]);
+                            const bf16x8 alo = __builtin_bit_cast(bf16x8, rec[cb * kRecordU4 + 64 + lane]);
+#pragma unroll
+                            for (int db = 0; db < DB; ++db) {
+                                acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bw[db], acc[cb][db], 0, 0, 0);
+                                acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bw[db], acc[cb][db], 0, 0, 0);
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) {
+                            f32x16 stp[DB];
+#pragma unroll
+                            for (int db = 0; db < DB; ++db)
+#pragma unroll
+                                for (int e = 0; e < 16; ++e) stp[db][e] = 0.f;
+#pragma unroll
+                            for (int p = 0; p < 2; ++p) {
+                                const uint4 av = rec[cb * kRecordU4 + 64 * p + lane];
+                                const float af[4] = {__uint_as_float(av.x), __uint_as_float(av.y),
+                                                     __uint_as_float(av.z), __uint_as_float(av.w)};
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                                    for (int db = 0; db < DB; ++db) {
+                                        const float bv = (float)((word[db] >> (16 * kk + 8 * p + 2 * q + h)) & 1u);
+                                        stp[db] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], bv, stp[db], 0, 0, 0);
+                                    }
+                                }
+                            }
+#pragma unroll
+                            for (int db = 0; db < DB; ++db) acc[cb][db] += stp[db];
+                        }
+                    }
+                }
+            }
+            if (kst == nst - 1) {
+                // ||G||^2 and sum_j |G_j| cabs_j over this chunk's covariates
+#pragma unroll
+                for (int db = 0; db < DB; ++db) {
+                    float s2 = 0.f, s1 = 0.f;
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        const int cov0 = 32 * (chunk * CB + cb) + 4 * h;
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const float g = acc[cb][db][r];
+                            s2 = fmaf(g, g, s2);
+                            s1 = fmaf(fabsf(g), a.cabs[cov0 + 8 * (r >> 2) + (r & 3)], s1);
+                        }
+                    }
+                    ss[db] += s2;
+                    sa[db] += s1;
+                }
+            }
+            if (gs + 1 < total) {
+#pragma unroll
+                for (int q = 0; q < PER_THREAD; ++q) sA[((gs + 1) & 1) * STAGE_U4 + tid + 256 * q] = pre[q];
+            }
+            __syncthreads();
+        }
+
+#pragma unroll
+        for (int db = 0; db < DB; ++db) {
+            const float s2 = ss[db] + __shfl_xor(ss[db], 32, 64);
+            const float s1 = sa[db] + __shfl_xor(sa[db], 32, 64);
+            const uint64_t idx = tile0 + wave * 32 * DB + 32 * db + j;
+            const bool live = h == 0 && idx < a.num;
+            const float m32 = a.scale * s2;
+            const float err = a.safety * (a.scale * (a.two_kappa * s1 + a.csq) + a.gamma_ss * m32);
+            if (a.out_m32) {
+                if (live) {
+                    a.out_m32[idx] = m32;
+                    a.out_err[idx] = err;
+                }
+            } else {
+                const float hi = (m32 + err) * (1.0f + 0x1p-21f);
+                const float lo = fmaxf((m32 - err) * (1.0f - 0x1p-21f), 0.0f);
+                const bool pass = live && (a.U == nullptr || lo <= *a.U);
+                const uint64_t bm = __ballot(pass);
+                if (bm) {
+                    const int first = (int)__builtin_ctzll(bm);
+                    uint32_t base = 0;
+                    if (lane == first) base = atomicAdd(a.cand_count, (uint32_t)__builtin_popcountll(bm));
+                    base = __shfl(base, first, 64);
+                    if (pass) {
+                        const uint32_t pos = base + __builtin_amdgcn_mbcnt_hi(
+                                                        (uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
+                        if (pos < a.cand_cap) {
+                            a.cand_key[pos] = a.keylist ? a.keylist[idx] : a.key_begin + idx;
+                            a.cand_hi[pos] = hi;
+                            a.cand_lo[pos] = lo;
+                            a.cand_m[pos] = m32;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Tile shapes: covariate blocks per chunk (CB) and 32-draw blocks per wave (DB).
+constexpr int cb_for(int prec) { return prec == RR_PREC_SPLIT_BF16 ? 4 : 2; }
+constexpr int db_for(int S) { return S <= 4 ? 2 : 1; }
+
+template <int PREC, int S>
+static size_t contract_lds() {
+    return sizeof(uint4) * 2 * kKStage * cb_for(PREC) * kRecordU4 +
+           sizeof(uint32_t) * (4 * 32 * db_for(S)) * (8 * S + 1);
+}
+
+template <int PREC, int S>
+static hipError_t launch_contract_t(const ContractArgs& a, int grid, hipStream_t st) {
+    auto k = contract_kernel<PREC, cb_for(PREC), db_for(S), S>;
+    const size_t lds = contract_lds<PREC, S>();
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_contract_p(int S, const ContractArgs& a, int grid, hipStream_t st) {
+    switch (S) {
+        case 1: return launch_contract_t<PREC, 1>(a, grid, st);
+        case 2: return launch_contract_t<PREC, 2>(a, grid, st);
+        case 4: return launch_contract_t<PREC, 4>(a, grid, st);
+        case 8: return launch_contract_t<PREC, 8>(a, grid, st);
+        case 16: return launch_contract_t<PREC, 16>(a, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_contract(int S, int prec, const ContractArgs& a, int grid, hipStream_t st) {
+    grid = std::max(1, grid);
+    return prec == RR_PREC_SPLIT_BF16 ? launch_contract_p<RR_PREC_SPLIT_BF16>(S, a, grid, st)
+                                      : launch_contract_p<RR_PREC_FP32>(S, a, grid, st);
+}
+
+int contract_tile(int S) { return 4 * 32 * db_for(S); }
+int draw_cb(int prec) { return cb_for(prec); }
+
+}  // namespace rr

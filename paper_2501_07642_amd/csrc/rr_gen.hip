@@ -1,0 +1,108 @@
+// Candidate generation: per-draw treated sets as bitmasks in HBM.
+//
+// Monte Carlo draws (section 2.3 generate_randomizations, "monte_carlo"; section 2.1
+// "Key-only storage"): draw b treats the n1 units with the smallest Philox-4x32-10 unit
+// keys (gen_mc_bits).  Exact enumeration (randomization_type = "exact"): draw r is the
+// treated set of colex rank r.  One wave per Monte Carlo draw, one lane per exact draw.
+#include <algorithm>
+
+#include "rr_internal.h"
+
+namespace rr {
+
+template <int S, bool EXACT>
+__global__ __launch_bounds__(256) void gen_kernel(GenArgs g) {
+    __shared__ uint32_t shist[4][256];
+    __shared__ uint2 slist[4][64];
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave, nw = (uint64_t)gridDim.x * 4;
+    if constexpr (EXACT) {
+        for (uint64_t base = gw * 64; base < g.num; base += nw * 64) {
+            const uint64_t idx = base + lane;
+            if (idx < g.num) {
+                const uint64_t key = g.keylist ? g.keylist[idx] : g.key_begin + idx;
+                const uint64_t m = colex_unrank_mask(key, g.n, g.n1, g.binom);
+                uint4* o = reinterpret_cast<uint4*>(g.out + idx * 8);
+                o[0] = make_uint4((uint32_t)m, (uint32_t)(m >> 32), 0u, 0u);
+                o[1] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+    } else {
+        for (uint64_t idx = gw; idx < g.num; idx += nw) {
+            const uint64_t key = g.keylist ? g.keylist[idx] : g.key_begin + idx;
+            gen_mc_bits<S>(g.seed, key, g.n, g.n1, shist[wave], slist[wave], g.out + idx * (8 * S));
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t st) {
+    grid = std::max(1, grid);
+    if (exact) {
+        hipLaunchKernelGGL((gen_kernel<1, true>), dim3(grid), dim3(256), 0, st, g);
+    } else {
+        switch (S) {
+            case 1: hipLaunchKernelGGL((gen_kernel<1, false>), dim3(grid), dim3(256), 0, st, g); break;
+            case 2: hipLaunchKernelGGL((gen_kernel<2, false>), dim3(grid), dim3(256), 0, st, g); break;
+            case 4: hipLaunchKernelGGL((gen_kernel<4, false>), dim3(grid), dim3(256), 0, st, g); break;
+            case 8: hipLaunchKernelGGL((gen_kernel<8, false>), dim3(grid), dim3(256), 0, st, g); break;
+            case 16: hipLaunchKernelGGL((gen_kernel<16, false>), dim3(grid), dim3(256), 0, st, g); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+int pow2_chunks(int n) {
+    int c = (n + kUnitsPerChunk - 1) / kUnitsPerChunk;
+    int S = 1;
+    while (S < c) S <<= 1;
+    return S;
+}
+
+
+// Regeneration of bitmasks (ceil(n/32) words per draw) from keys: one wave per draw.
+template <int S, bool EXACT>
+__global__ __launch_bounds__(256) void regen_kernel(const uint64_t* keys, uint64_t K, uint64_t seed,
+                                                    int n, int n1, const uint64_t* binom,
+                                                    uint32_t* out, int nw) {
+    __shared__ uint32_t sbits[4][8 * kMaxS];
+    __shared__ uint32_t shist[4][256];
+    __shared__ uint2 slist[4][64];
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    for (uint64_t k = (uint64_t)blockIdx.x * 4 + wave; k < K; k += (uint64_t)gridDim.x * 4) {
+        if constexpr (EXACT) {
+            if (lane == 0) {
+                const uint64_t m = colex_unrank_mask(keys[k], n, n1, binom);
+                sbits[wave][0] = (uint32_t)m;
+                sbits[wave][1] = (uint32_t)(m >> 32);
+            }
+        } else {
+            gen_mc_bits<S>(seed, keys[k], n, n1, shist[wave], slist[wave], sbits[wave]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int w = lane; w < nw; w += 64) out[k * nw + w] = sbits[wave][w];
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+hipError_t launch_regen(int S, bool exact, const uint64_t* keys, uint64_t K, uint64_t seed,
+                        int n, int n1, const uint64_t* binom, uint32_t* out, int nw, int grid,
+                        hipStream_t st) {
+    if (exact) {
+        hipLaunchKernelGGL((regen_kernel<1, true>), dim3(grid), dim3(256), 0, st, keys, K, seed, n, n1, binom, out, nw);
+    } else {
+        switch (S) {
+            case 1: hipLaunchKernelGGL((regen_kernel<1, false>), dim3(grid), dim3(256), 0, st, keys, K, seed, n, n1, binom, out, nw); break;
+            case 2: hipLaunchKernelGGL((regen_kernel<2, false>), dim3(grid), dim3(256), 0, st, keys, K, seed, n, n1, binom, out, nw); break;
+            case 4: hipLaunchKernelGGL((regen_kernel<4, false>), dim3(grid), dim3(256), 0, st, keys, K, seed, n, n1, binom, out, nw); break;
+            case 8: hipLaunchKernelGGL((regen_kernel<8, false>), dim3(grid), dim3(256), 0, st, keys, K, seed, n, n1, binom, out, nw); break;
+            case 16: hipLaunchKernelGGL((regen_kernel<16, false>), dim3(grid), dim3(256), 0, st, keys, K, seed, n, n1, binom, out, nw); break;
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rr

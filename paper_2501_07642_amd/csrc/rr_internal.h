@@ -54,18 +54,29 @@ struct Problem {
     // workspace for the draw pipeline (grown on demand)
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    hipStream_t gen_stream = nullptr;     // internal stream of the generation kernels
+    std::vector<hipEvent_t> events;       // chunk ordering and timing
 };
 
 
 // ---------------------------------------------------------------------------------------
-// Kernel argument blocks (shared by the draw kernels and the pipeline).
-struct DrawArgs {
+// Kernel argument blocks (shared by the kernels and the pipeline).
+struct GenArgs {
+    uint64_t seed, key_begin, num;
+    const uint64_t* keylist;  // non-null: keys of the draws; else key_begin + index
+    const uint64_t* binom;    // exact mode: C(i, t), i <= 64, t <= 32
+    int n, n1;
+    uint32_t* out;            // 8 S words per draw
+};
+
+struct ContractArgs {
+    const uint32_t* bits;     // 8 S words per draw (from the generation kernel)
+    uint64_t num;             // draws in this launch
+    uint64_t key_begin;       // key of draw i is key_begin + i, or keylist[i]
+    const uint64_t* keylist;
     const uint4* op;          // operand records, ks * ncb records of kRecordU4 uint4
     const float* cabs;        // 32 * ncb
-    const uint64_t* binom;    // exact mode: C(i, t), i <= 64, t <= 32
-    const uint64_t* keylist;  // list generation: keys of the draws
-    uint64_t seed, key_begin, num;
-    int n, n1, ks, ncb;
+    int n, ks, ncb;
     float scale;              // n / (n1 n0)
     float two_kappa;          // 2 * kappa: |G32_j - G_j| <= kappa * cabs_j
     float csq;                // kappa^2 * sum_j cabs_j^2

@@ -24,11 +24,12 @@
 
 namespace rr {
 
-hipError_t launch_draw(int S, int prec, bool exact, bool from_list, const DrawArgs& a, int grid, hipStream_t st);
+hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t st);
+hipError_t launch_contract(int S, int prec, const ContractArgs& a, int grid, hipStream_t st);
+int contract_tile(int S);
 hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hipStream_t st);
 hipError_t launch_regen(int S, bool exact, const uint64_t* keys, uint64_t K, uint64_t seed, int n, int n1,
                         const uint64_t* binom, uint32_t* out, int nw, int grid, hipStream_t st);
-int draw_tile();
 int draw_cb(int prec);
 
 
@@ -41,7 +42,7 @@ static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 
 struct Timing {
-    double total_ms = 0, draw_ms = 0;
+    double total_ms = 0, contract_ms = 0, gen_ms = 0;
     int64_t launches = 0;
     uint64_t band = 0;
 };
@@ -408,12 +409,13 @@ struct WS {
     uint8_t* band_work;
     uint64_t* sk[2];
     uint32_t* si[2];
+    uint32_t* bits[2];
     uint32_t cand_cap, acc_cap, band_cap;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint32_t band_cap, WS* w) {
+static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint32_t band_cap, size_t bits_words, WS* w) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -427,6 +429,7 @@ static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint
     const size_t o_bk = take(8ull * band_cap), o_bm = take(8ull * band_cap), o_bw = take(band_cap);
     const size_t o_s0 = take(8ull * acc_cap), o_s1 = take(8ull * acc_cap), o_i0 = take(4ull * acc_cap),
                  o_i1 = take(4ull * acc_cap);
+    const size_t o_b0 = take(4ull * bits_words), o_b1 = take(4ull * bits_words);
     if (off > P.ws_bytes) {
         if (P.ws) hipFree(P.ws);
         P.ws = nullptr;
@@ -450,6 +453,8 @@ static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint
     w->sk[1] = (uint64_t*)(b + o_s1);
     w->si[0] = (uint32_t*)(b + o_i0);
     w->si[1] = (uint32_t*)(b + o_i1);
+    w->bits[0] = (uint32_t*)(b + o_b0);
+    w->bits[1] = (uint32_t*)(b + o_b1);
     w->cand_cap = cand_cap;
     w->acc_cap = acc_cap;
     w->band_cap = band_cap;
@@ -515,12 +520,11 @@ static int device_cus(int dev) {
     return cus;
 }
 
-static DrawArgs make_draw_args(const Problem& P, int prec, const Bound& b) {
-    DrawArgs a{};
+static ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b) {
+    ContractArgs a{};
     a.op = prec == RR_PREC_SPLIT_BF16 ? P.op_split : P.op_f32;
     a.cabs = P.cabs;
     a.n = (int)P.n;
-    a.n1 = (int)P.n1;
     a.ks = (int)P.ks;
     a.ncb = (int)P.ncb;
     a.scale = (float)P.scale;
@@ -531,11 +535,17 @@ static DrawArgs make_draw_args(const Problem& P, int prec, const Bound& b) {
     return a;
 }
 
-static int draw_grid(const Problem& P, uint64_t num) {
-    const uint64_t wave_tiles = (num + draw_tile() - 1) / draw_tile();
-    const uint64_t blocks = (wave_tiles + 3) / 4;
-    const uint64_t cap = (uint64_t)device_cus(P.device) * 2;
-    return (int)std::max<uint64_t>(1, std::min<uint64_t>(blocks, cap));
+// Per-handle resources of the two-stream pipeline: generation runs on an internal stream
+// (default priority) and overlaps the contraction of the previous chunk on the caller's
+// stream; events order the double-buffered bitmask chunks.
+static rr_status ensure_streams(Problem& P, size_t nevents) {
+    if (!P.gen_stream) RR_HIP(hipStreamCreateWithFlags(&P.gen_stream, hipStreamNonBlocking));
+    while (P.events.size() < nevents) {
+        hipEvent_t e;
+        RR_HIP(hipEventCreate(&e));
+        P.events.push_back(e);
+    }
+    return RR_OK;
 }
 
 static hipError_t run_select(WS& w, hipStream_t st) {
@@ -579,14 +589,19 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
         set_error("rr_draw: threshold is NaN");
         return RR_E_ARG;
     }
-    const uint64_t chunk0 = std::min<uint64_t>(N, std::max<uint64_t>(1u << 22, 8 * k));
-    const uint64_t chunk = 1ull << 25;
-    const uint32_t cand_cap = (uint32_t)std::max<uint64_t>(chunk0 + (1u << 20), 1u << 23);
+    // Chunks of draws: the bitmasks of chunk c are generated on the internal stream while
+    // chunk c - 1 is contracted on the caller's stream.
+    uint64_t chunk = std::min<uint64_t>(std::max<uint64_t>((N + 3) / 4, 1u << 16), 1u << 20);
+    chunk = std::min<uint64_t>(chunk, N);
+    const uint64_t nchunks = (N + chunk - 1) / chunk;
+    const size_t wpd = 8ull * P.S;
+    const uint32_t cand_cap = (uint32_t)std::max<uint64_t>(chunk + (1u << 20), 1u << 23);
     const uint32_t acc_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(capacity, 1), cand_cap);
     const uint32_t band_cap = 1u << 20;
     WS w;
-    rr_status s = ensure_ws(P, cand_cap, acc_cap, band_cap, &w);
+    rr_status s = ensure_ws(P, cand_cap, acc_cap, band_cap, chunk * wpd, &w);
     if (s != RR_OK) return s;
+    if ((s = ensure_streams(P, 4 * nchunks + 5)) != RR_OK) return s;
     std::vector<float> ch;
     if ((s = cabs_host(P, ch, st)) != RR_OK) return s;
     const Bound b = bound_constants(P, prec, ch);
@@ -608,50 +623,69 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
         }
         RR_HIP(hipMemcpyAsync(w.ctl, &init, offsetof(Ctl, hist), hipMemcpyHostToDevice, st));
     }
-    hipEvent_t e0, e1;
-    RR_HIP(hipEventCreate(&e0));
-    RR_HIP(hipEventCreate(&e1));
-    double draw_ms = 0;
-    int64_t launches = 0;
-    DrawArgs a = make_draw_args(P, prec, b);
-    a.binom = binom;
-    a.seed = seed;
+    hipEvent_t* ev = P.events.data();
+    hipEvent_t ev_start = ev[0], *ev_ready = ev + 1, *ev_free = ev + 3;
+    hipEvent_t* ev_t = ev + 5;   // per chunk: contract start/end, gen start/end
+    const int cus = device_cus(P.device);
+    GenArgs g{};
+    g.seed = seed;
+    g.binom = binom;
+    g.n = (int)P.n;
+    g.n1 = (int)P.n1;
+    ContractArgs a = make_contract_args(P, prec, b);
     a.cand_key = w.cand_key;
     a.cand_hi = w.cand_hi;
     a.cand_lo = w.cand_lo;
     a.cand_m = w.cand_m;
     a.cand_count = &w.ctl->cand_count;
     a.cand_cap = cand_cap;
-    uint64_t done = 0;
-    bool first = true;
-    while (done < N) {
-        const uint64_t num = std::min<uint64_t>(N - done, first ? chunk0 : chunk);
-        a.key_begin = key_begin + done;
+    RR_HIP(hipEventRecord(ev_start, st));
+    RR_HIP(hipStreamWaitEvent(P.gen_stream, ev_start, 0));
+    for (uint64_t c = 0; c < nchunks; ++c) {
+        const int bsel = (int)(c & 1);
+        const uint64_t off = c * chunk;
+        const uint64_t num = std::min<uint64_t>(N - off, chunk);
+        if (c >= 2) RR_HIP(hipStreamWaitEvent(P.gen_stream, ev_free[bsel], 0));
+        g.key_begin = key_begin + off;
+        g.num = num;
+        g.out = w.bits[bsel];
+        RR_HIP(hipEventRecord(ev_t[4 * c + 2], P.gen_stream));
+        const uint64_t gen_units = exact ? (num + 63) / 64 : num;
+        RR_HIP(launch_gen(P.S, exact, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * 2),
+                          P.gen_stream));
+        RR_HIP(hipEventRecord(ev_t[4 * c + 3], P.gen_stream));
+        RR_HIP(hipEventRecord(ev_ready[bsel], P.gen_stream));
+        RR_HIP(hipStreamWaitEvent(st, ev_ready[bsel], 0));
+        a.bits = w.bits[bsel];
         a.num = num;
-        a.U = (mode == RR_MODE_QUANTILE && first) ? nullptr : &w.ctl->U;
-        RR_HIP(hipEventRecord(e0, st));
-        RR_HIP(launch_draw(P.S, prec, exact, false, a, draw_grid(P, num), st));
-        RR_HIP(hipEventRecord(e1, st));
-        ++launches;
-        done += num;
-        first = false;
-        if (mode == RR_MODE_QUANTILE && done < N) {
+        a.key_begin = key_begin + off;
+        a.U = (mode == RR_MODE_QUANTILE && c == 0) ? nullptr : &w.ctl->U;
+        const uint64_t tiles = (num + contract_tile(P.S) - 1) / contract_tile(P.S);
+        RR_HIP(hipEventRecord(ev_t[4 * c], st));
+        RR_HIP(launch_contract(P.S, prec, a, (int)std::min<uint64_t>(tiles, (uint64_t)cus), st));
+        RR_HIP(hipEventRecord(ev_t[4 * c + 1], st));
+        RR_HIP(hipEventRecord(ev_free[bsel], st));
+        if (mode == RR_MODE_QUANTILE && c + 1 < nchunks && (c == 0 || c % 8 == 7)) {
             RR_HIP(run_select(w, st));
             hipLaunchKernelGGL(update_U_kernel, dim3(1), dim3(1), 0, st, w.ctl);
             RR_HIP(hipGetLastError());
         }
-        RR_HIP(hipEventSynchronize(e1));
-        float ms = 0;
-        RR_HIP(hipEventElapsedTime(&ms, e0, e1));
-        draw_ms += ms;
     }
+    RR_HIP(hipStreamSynchronize(st));
+    double contract_ms = 0, gen_ms = 0;
+    for (uint64_t c = 0; c < nchunks; ++c) {
+        float m1 = 0, m2 = 0;
+        RR_HIP(hipEventElapsedTime(&m1, ev_t[4 * c], ev_t[4 * c + 1]));
+        RR_HIP(hipEventElapsedTime(&m2, ev_t[4 * c + 2], ev_t[4 * c + 3]));
+        contract_ms += m1;
+        gen_ms += m2;
+    }
+    const int64_t launches = (int64_t)nchunks;
     Ctl hc;
     RR_HIP(hipMemcpyAsync(&hc, w.ctl, offsetof(Ctl, hist), hipMemcpyDeviceToHost, st));
     RR_HIP(hipStreamSynchronize(st));
     if (hc.cand_count > cand_cap) {
         set_error("rr_draw: candidate buffer overflow (too many draws near the boundary)");
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
         return RR_E_UNSUPPORTED;
     }
     if (mode == RR_MODE_QUANTILE) RR_HIP(run_select(w, st));
@@ -681,8 +715,6 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
     RR_HIP(hipGetLastError());
     RR_HIP(hipMemcpyAsync(&hc, w.ctl, offsetof(Ctl, hist), hipMemcpyDeviceToHost, st));
     RR_HIP(hipStreamSynchronize(st));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     if (hc.sel_fail || hc.guard_fail) {
         set_error("rr_draw: selection failed (guard band inconsistent)");
         return RR_E_DEVICE;
@@ -717,7 +749,8 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
         RR_HIP(hipStreamSynchronize(st));
     }
     *h_count = K;
-    g_timing.draw_ms = draw_ms;
+    g_timing.contract_ms = contract_ms;
+    g_timing.gen_ms = gen_ms;
     g_timing.launches = launches;
     g_timing.band = hc.band_count;
     g_timing.total_ms =
@@ -752,6 +785,8 @@ void rr_free(rr_problem* p) {
     hipFree(P.op_f32);
     hipFree(P.cabs);
     hipFree(P.ws);
+    for (hipEvent_t e : P.events) hipEventDestroy(e);
+    if (P.gen_stream) hipStreamDestroy(P.gen_stream);
     delete p;
 }
 
@@ -831,14 +866,31 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
         rr_status s = cabs_host(P, ch, st);
         if (s != RR_OK) return s;
         const Bound b = bound_constants(P, precision, ch);
-        DrawArgs a = make_draw_args(P, precision, b);
-        a.binom = binom;
-        a.keylist = d_keys;
-        a.seed = seed;
+        uint32_t* bits = nullptr;
+        RR_HIP(hipMalloc(&bits, sizeof(uint32_t) * 8 * P.S * K));
+        GenArgs g{};
+        g.seed = seed;
+        g.num = K;
+        g.keylist = d_keys;
+        g.binom = binom;
+        g.n = (int)P.n;
+        g.n1 = (int)P.n1;
+        g.out = bits;
+        const int cus = device_cus(P.device);
+        const uint64_t gen_units = exact ? (K + 63) / 64 : K;
+        hipError_t e = launch_gen(P.S, exact != 0, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * 2), st);
+        ContractArgs a = make_contract_args(P, precision, b);
+        a.bits = bits;
         a.num = K;
+        a.keylist = d_keys;
         a.out_m32 = d_M32;
         a.out_err = d_err;
-        RR_HIP(launch_draw(P.S, precision, exact != 0, true, a, draw_grid(P, K), st));
+        const uint64_t tiles = (K + contract_tile(P.S) - 1) / contract_tile(P.S);
+        if (e == hipSuccess) e = launch_contract(P.S, precision, a, (int)std::min<uint64_t>(tiles, (uint64_t)cus), st);
+        hipError_t e2 = hipStreamSynchronize(st);
+        hipFree(bits);
+        RR_HIP(e);
+        RR_HIP(e2);
     }
     if (d_M64) {
         uint32_t* cnt = nullptr;
@@ -874,7 +926,7 @@ rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob, const uin
         set_error("rr_draw_balance_batched: invalid argument");
         return RR_E_ARG;
     }
-    double total = 0, dk = 0;
+    double total = 0, ck = 0, gk = 0;
     int64_t launches = 0;
     uint64_t band = 0;
     for (int64_t i = 0; i < nprob; ++i) {
@@ -886,20 +938,24 @@ rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob, const uin
                                     d_keys[i], d_M[i], nullptr, capacity, &h_counts[i], (hipStream_t)stream);
         if (s != RR_OK) return s;
         total += g_timing.total_ms;
-        dk += g_timing.draw_ms;
+        ck += g_timing.contract_ms;
+        gk += g_timing.gen_ms;
         launches += g_timing.launches;
         band += g_timing.band;
     }
     g_timing.total_ms = total;
-    g_timing.draw_ms = dk;
+    g_timing.contract_ms = ck;
+    g_timing.gen_ms = gk;
     g_timing.launches = launches;
     g_timing.band = band;
     return RR_OK;
 }
 
-rr_status rr_last_timing(double* total_ms, double* draw_kernel_ms, int64_t* draw_launches, uint64_t* band_size) {
+rr_status rr_last_timing(double* total_ms, double* contract_ms, double* gen_ms, int64_t* draw_launches,
+                         uint64_t* band_size) {
     if (total_ms) *total_ms = g_timing.total_ms;
-    if (draw_kernel_ms) *draw_kernel_ms = g_timing.draw_ms;
+    if (contract_ms) *contract_ms = g_timing.contract_ms;
+    if (gen_ms) *gen_ms = g_timing.gen_ms;
     if (draw_launches) *draw_launches = g_timing.launches;
     if (band_size) *band_size = g_timing.band;
     return RR_OK;
