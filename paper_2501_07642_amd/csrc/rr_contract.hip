@@ -5,10 +5,11 @@
 // draw) gives M = n / (n1 n0) ||G||^2 (chi^2_d scale).  Centring makes the control sum
 // redundant: sum_{i in C} X~_i = -G.
 //
-// One workgroup (4 waves) takes a tile of 128 DB draws; wave w owns draws
+// One workgroup (NW waves) takes a tile of 32 NW DB draws; wave w owns draws
 // [32 DB w, 32 DB (w+1)).  G^T = X~^T W^T is computed per covariate chunk of 32 CB: the A
 // operand (32 covariates x 16 units of X~^T) comes from the precomputed operand records,
-// staged through LDS two K steps at a time (double-buffered, shared by the four waves);
+// staged from global memory straight into LDS four K steps at a time (double-buffered,
+// shared by the waves of the workgroup);
 // the B operand (16 units x 32 draws of W^T) is expanded from the tile's bitmasks in LDS.
 // In an output block, lane l holds draw l % 32 and 16 covariates, so ||G||^2 and the error
 // bound are reduced in registers and across the two lane halves.
@@ -24,7 +25,7 @@ namespace rr {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 
-constexpr int kKStage = 2;   // K steps per LDS stage
+constexpr int kKStage = 4;   // K steps per LDS stage
 
 __device__ __forceinline__ uint4 expand_bf16(uint32_t x) {
     // 8 bits -> 8 BF16 values (1.0 = 0x3F80 or 0): bit 2k -> low half of dword k,
@@ -38,47 +39,49 @@ __device__ __forceinline__ uint4 expand_bf16(uint32_t x) {
     return r;
 }
 
-template <int PREC, int CB, int DB, int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+template <int PREC, int NW, int CB, int DB, int S>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 2)))
 void contract_kernel(ContractArgs a) {
-    constexpr int TILE = 4 * 32 * DB;
+    constexpr int TILE = NW * 32 * DB;
     constexpr int WSTR = 8 * S + 1;                       // +1: 32 draws hit 32 banks
-    constexpr int STAGE_U4 = kKStage * CB * kRecordU4;    // uint4 per stage
-    constexpr int PER_THREAD = STAGE_U4 / 256;
+    constexpr int REC = kKStage * CB * 2;                 // 1 KB plane records per stage
+    constexpr int STAGE_U4 = REC * 64;
+    static_assert(REC % NW == 0, "each wave loads the same number of plane records");
     extern __shared__ uint4 smem4[];
-    uint4* sA = smem4;                                     // [2][kKStage][CB][128]
+    uint4* sA = smem4;                                     // [2][kKStage][CB][2 planes][64 lanes]
     uint32_t* sbits = reinterpret_cast<uint32_t*>(smem4 + 2 * STAGE_U4);   // [TILE][WSTR]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, j = lane & 31;
     const int nchunks = a.ncb / CB;
-    const int nst = (a.ks + kKStage - 1) / kKStage;
+    const int nst = a.ks / kKStage;
     const int total = nchunks * nst;
     const uint64_t ntiles = (a.num + TILE - 1) / TILE;
 
-    auto load_stage = [&](int gs, uint4* r) {
+    // Stage gs = (chunk, K stage) goes straight from global memory to LDS buffer `buf`;
+    // wave w moves plane records w, w + 4, ... (64 lanes x 16 B each).
+    auto issue_stage = [&](int gs, int buf) {
         const int chunk = gs / nst, kst = gs % nst;
 #pragma unroll
-        for (int q = 0; q < PER_THREAD; ++q) {
-            const int e = tid + 256 * q;
-            const int kk = e / (CB * kRecordU4), rem = e % (CB * kRecordU4);
-            const int cb = rem / kRecordU4, w = rem % kRecordU4;
-            const int k = kst * kKStage + kk;
-            r[q] = k < a.ks ? a.op[((size_t)k * a.ncb + chunk * CB + cb) * kRecordU4 + w] : make_uint4(0, 0, 0, 0);
+        for (int r = wave; r < REC; r += NW) {
+            const int kk = r / (CB * 2), cb = (r >> 1) % CB, p = r & 1;
+            const int k = kst * kKStage + kk;     // ks is a multiple of kKStage
+            const uint4* src = a.op + ((size_t)k * a.ncb + chunk * CB + cb) * kRecordU4 + 64 * p + lane;
+            __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(sA + buf * STAGE_U4 + r * 64), 16, 0, 0);
         }
     };
 
     for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const uint64_t tile0 = t * TILE;
-        for (int e = tid; e < TILE * 8 * S; e += 256) {
+        for (int e = tid; e < TILE * 8 * S; e += NW * 64) {
             const int dr = e / (8 * S), w = e % (8 * S);
             const uint64_t idx = tile0 + dr;
             sbits[dr * WSTR + w] = idx < a.num ? a.bits[idx * (8 * S) + w] : 0u;
         }
-        uint4 pre[PER_THREAD];
-        load_stage(0, pre);
-#pragma unroll
-        for (int q = 0; q < PER_THREAD; ++q) sA[tid + 256 * q] = pre[q];
+        issue_stage(0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
 
         float ss[DB], sa[DB];
@@ -97,31 +100,39 @@ void contract_kernel(ContractArgs a) {
 #pragma unroll
                         for (int e = 0; e < 16; ++e) acc[cb][db][e] = 0.f;
             }
-            if (gs + 1 < total) load_stage(gs + 1, pre);
+            if (gs + 1 < total) issue_stage(gs + 1, (gs + 1) & 1);
             const uint4* st = sA + (gs & 1) * STAGE_U4;
-            uint32_t word[DB];
+            // bitmask words of this stage: units 64 kst .. 64 kst + 63
+            uint32_t wlo[DB], whi[DB];
 #pragma unroll
-            for (int db = 0; db < DB; ++db) word[db] = myb[32 * db * WSTR + kst];   // units 32 kst .. +31
+            for (int db = 0; db < DB; ++db) {
+                wlo[db] = myb[32 * db * WSTR + 2 * kst];
+                whi[db] = myb[32 * db * WSTR + 2 * kst + 1];
+            }
+            if constexpr (PREC == RR_PREC_SPLIT_BF16) {
 #pragma unroll
-            for (int kk = 0; kk < kKStage; ++kk) {
-                if (kst * kKStage + kk < a.ks) {
-                    const uint4* rec = st + kk * CB * kRecordU4;
-                    if constexpr (PREC == RR_PREC_SPLIT_BF16) {
-                        bf16x8 bw[DB];
+                for (int kk = 0; kk < kKStage; ++kk) {
+                    bf16x8 B[DB];
 #pragma unroll
-                        for (int db = 0; db < DB; ++db)
-                            bw[db] = __builtin_bit_cast(bf16x8, expand_bf16((word[db] >> (16 * kk + 8 * h)) & 0xFFu));
+                    for (int db = 0; db < DB; ++db) {
+                        const uint32_t w = kk < 2 ? wlo[db] : whi[db];
+                        B[db] = __builtin_bit_cast(bf16x8, expand_bf16((w >> (16 * (kk & 1) + 8 * h)) & 0xFFu));
+                    }
 #pragma unroll
-                        for (int cb = 0; cb < CB; ++cb) {
-                            const bf16x8 ahi = __builtin_bit_cast(bf16x8, rec[cb * kRecordU4 + lane]);
-                            const bf16x8 alo = __builtin_bit_cast(bf16x8, rec[cb * kRecordU4 + 64 + lane]);
+                    for (int cb = 0; cb < CB; ++cb) {
 #pragma unroll
-                            for (int db = 0; db < DB; ++db) {
-                                acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bw[db], acc[cb][db], 0, 0, 0);
-                                acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bw[db], acc[cb][db], 0, 0, 0);
-                            }
+                        for (int p = 0; p < 2; ++p) {
+                            const bf16x8 A = __builtin_bit_cast(bf16x8, st[((kk * CB + cb) * 2 + p) * 64 + lane]);
+#pragma unroll
+                            for (int db = 0; db < DB; ++db)
+                                acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B[db], acc[cb][db], 0, 0, 0);
                         }
-                    } else {
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < kKStage; ++kk) {
+                    {
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb) {
                             f32x16 stp[DB];
@@ -131,14 +142,15 @@ void contract_kernel(ContractArgs a) {
                                 for (int e = 0; e < 16; ++e) stp[db][e] = 0.f;
 #pragma unroll
                             for (int p = 0; p < 2; ++p) {
-                                const uint4 av = rec[cb * kRecordU4 + 64 * p + lane];
+                                const uint4 av = st[((kk * CB + cb) * 2 + p) * 64 + lane];
                                 const float af[4] = {__uint_as_float(av.x), __uint_as_float(av.y),
                                                      __uint_as_float(av.z), __uint_as_float(av.w)};
 #pragma unroll
                                 for (int q = 0; q < 4; ++q) {
 #pragma unroll
                                     for (int db = 0; db < DB; ++db) {
-                                        const float bv = (float)((word[db] >> (16 * kk + 8 * p + 2 * q + h)) & 1u);
+                                        const uint32_t w = kk < 2 ? wlo[db] : whi[db];
+                                        const float bv = (float)((w >> (16 * (kk & 1) + 8 * p + 2 * q + h)) & 1u);
                                         stp[db] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], bv, stp[db], 0, 0, 0);
                                     }
                                 }
@@ -168,10 +180,7 @@ void contract_kernel(ContractArgs a) {
                     sa[db] += s1;
                 }
             }
-            if (gs + 1 < total) {
-#pragma unroll
-                for (int q = 0; q < PER_THREAD; ++q) sA[((gs + 1) & 1) * STAGE_U4 + tid + 256 * q] = pre[q];
-            }
+            __builtin_amdgcn_s_waitcnt(0);     // this wave's loads of the next stage landed
             __syncthreads();
         }
 
@@ -215,22 +224,27 @@ void contract_kernel(ContractArgs a) {
 }
 
 // Tile shapes: covariate blocks per chunk (CB) and 32-draw blocks per wave (DB).
-constexpr int cb_for(int prec) { return prec == RR_PREC_SPLIT_BF16 ? 4 : 2; }
-constexpr int db_for(int S) { return S <= 4 ? 2 : 1; }
+// Tile shapes.  Split BF16: 8 waves (two per SIMD, so one wave's bit expansion on the
+// VALU overlaps the other's MFMA), each with 2 x DB accumulator blocks of 32x32 (<= 128
+// registers, leaving room for the generation kernel's waves); FP32: 4 waves of 2 x DB blocks
+// plus a per-K-step block set.  Fewer draws per wave for long bitmasks (LDS).
+constexpr int nw_for(int prec, int S) { return prec == RR_PREC_SPLIT_BF16 && S <= 8 ? 8 : 4; }
+constexpr int cb_for(int, int) { return 2; }
+constexpr int db_for(int prec, int S) { return prec == RR_PREC_SPLIT_BF16 ? (S <= 4 ? 2 : 1) : (S <= 8 ? 2 : 1); }
 
 template <int PREC, int S>
 static size_t contract_lds() {
-    return sizeof(uint4) * 2 * kKStage * cb_for(PREC) * kRecordU4 +
-           sizeof(uint32_t) * (4 * 32 * db_for(S)) * (8 * S + 1);
+    return sizeof(uint4) * 2 * kKStage * cb_for(PREC, S) * kRecordU4 +
+           sizeof(uint32_t) * (nw_for(PREC, S) * 32 * db_for(PREC, S)) * (8 * S + 1);
 }
 
 template <int PREC, int S>
 static hipError_t launch_contract_t(const ContractArgs& a, int grid, hipStream_t st) {
-    auto k = contract_kernel<PREC, cb_for(PREC), db_for(S), S>;
+    auto k = contract_kernel<PREC, nw_for(PREC, S), cb_for(PREC, S), db_for(PREC, S), S>;
     const size_t lds = contract_lds<PREC, S>();
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * nw_for(PREC, S)), lds, st, a);
     return hipGetLastError();
 }
 
@@ -252,7 +266,7 @@ hipError_t launch_contract(int S, int prec, const ContractArgs& a, int grid, hip
                                       : launch_contract_p<RR_PREC_FP32>(S, a, grid, st);
 }
 
-int contract_tile(int S) { return 4 * 32 * db_for(S); }
-int draw_cb(int prec) { return cb_for(prec); }
+int contract_tile(int prec, int S) { return nw_for(prec, S) * 32 * db_for(prec, S); }
+int draw_cb(int prec, int S) { return cb_for(prec, S); }
 
 }  // namespace rr

@@ -41,7 +41,7 @@ struct Problem {
     double ridge_rel = 0, lambda = 0;
     int S = 0;             // 256-unit chunks per draw: ceil(n / 256)
     int wstride = 0;       // uint32 words per draw bitmask in the internal layout: 8 * S
-    int64_t ks = 0;        // K steps of 16 units: ceil(n / 16)
+    int64_t ks = 0;        // K steps of 16 units, a multiple of 4 (units >= n are zero)
     int64_t ncb = 0;       // covariate blocks of 32 (padded)
     double scale = 0;      // n / (n1 n0)
     // device buffers

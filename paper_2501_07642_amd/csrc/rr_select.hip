@@ -26,11 +26,11 @@ namespace rr {
 
 hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t st);
 hipError_t launch_contract(int S, int prec, const ContractArgs& a, int grid, hipStream_t st);
-int contract_tile(int S);
+int contract_tile(int prec, int S);
 hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hipStream_t st);
 hipError_t launch_regen(int S, bool exact, const uint64_t* keys, uint64_t K, uint64_t seed, int n, int n1,
                         const uint64_t* binom, uint32_t* out, int nw, int grid, hipStream_t st);
-int draw_cb(int prec);
+int draw_cb(int prec, int S);
 
 
 constexpr double kEpsTie = 1e-10;
@@ -493,7 +493,7 @@ Bound bound_constants(const Problem& P, int prec, const std::vector<float>& cabs
         kappa = gamma_m(16.0 + ks) * (1.0 + 0x1p-23) + 0x1p-24;
     double c2 = 0.0;
     for (float c : cabs_host) c2 += (double)c * (double)c;
-    const int cb = draw_cb(prec);
+    const int cb = draw_cb(prec, P.S);
     const int chunks = (int)((P.ncb + cb - 1) / cb);
     const double depth_ss = 16.0 * cb + chunks + 4.0;
     Bound b;
@@ -660,7 +660,7 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
         a.num = num;
         a.key_begin = key_begin + off;
         a.U = (mode == RR_MODE_QUANTILE && c == 0) ? nullptr : &w.ctl->U;
-        const uint64_t tiles = (num + contract_tile(P.S) - 1) / contract_tile(P.S);
+        const uint64_t tiles = (num + contract_tile(prec, P.S) - 1) / contract_tile(prec, P.S);
         RR_HIP(hipEventRecord(ev_t[4 * c], st));
         RR_HIP(launch_contract(P.S, prec, a, (int)std::min<uint64_t>(tiles, (uint64_t)cus), st));
         RR_HIP(hipEventRecord(ev_t[4 * c + 1], st));
@@ -885,7 +885,7 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
         a.keylist = d_keys;
         a.out_m32 = d_M32;
         a.out_err = d_err;
-        const uint64_t tiles = (K + contract_tile(P.S) - 1) / contract_tile(P.S);
+        const uint64_t tiles = (K + contract_tile(precision, P.S) - 1) / contract_tile(precision, P.S);
         if (e == hipSuccess) e = launch_contract(P.S, precision, a, (int)std::min<uint64_t>(tiles, (uint64_t)cus), st);
         hipError_t e2 = hipStreamSynchronize(st);
         hipFree(bits);
