@@ -11,8 +11,8 @@
 // staged from global memory straight into LDS four K steps at a time (double-buffered,
 // shared by the waves of the workgroup);
 // the B operand (16 units x 32 draws of W^T) is expanded from the tile's bitmasks in LDS.
-// In an output block, lane l holds draw l % 32 and 16 covariates, so ||G||^2 and the error
-// bound are reduced in registers and across the two lane halves.
+// In an output block, lane l holds draw l % 32 and 16 covariates, so ||G||^2 is reduced in
+// registers and across the two lane halves; the error bound needs only ||G||.
 //
 //   split BF16: X~ = hi + lo, two 32x32x16 BF16 MFMA per K step into one FP32 accumulator;
 //   FP32:       32x32x2 FP32 MFMA; each K step starts from zero and is added on the VALU.
@@ -25,7 +25,7 @@ namespace rr {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 
-constexpr int kKStage = 4;   // K steps per LDS stage
+constexpr int kKStage = kKStepsPerStage;   // K steps per LDS stage
 
 __device__ __forceinline__ uint4 expand_bf16(uint32_t x) {
     // 8 bits -> 8 BF16 values (1.0 = 0x3F80 or 0): bit 2k -> low half of dword k,
@@ -56,7 +56,7 @@ void contract_kernel(ContractArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, j = lane & 31;
     const int nchunks = a.ncb / CB;
-    const int nst = a.ks / kKStage;
+    const int nst = a.ks / kKStage;          // ks is a multiple of kKStage
     const int total = nchunks * nst;
     const uint64_t ntiles = (a.num + TILE - 1) / TILE;
 
@@ -84,9 +84,9 @@ void contract_kernel(ContractArgs a) {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
 
-        float ss[DB], sa[DB];
+        float ss[DB];
 #pragma unroll
-        for (int db = 0; db < DB; ++db) ss[db] = sa[db] = 0.f;
+        for (int db = 0; db < DB; ++db) ss[db] = 0.f;
         f32x16 acc[CB][DB];
         const uint32_t* myb = sbits + (wave * 32 * DB + j) * WSTR;
 
@@ -102,31 +102,45 @@ void contract_kernel(ContractArgs a) {
             }
             if (gs + 1 < total) issue_stage(gs + 1, (gs + 1) & 1);
             const uint4* st = sA + (gs & 1) * STAGE_U4;
-            // bitmask words of this stage: units 64 kst .. 64 kst + 63
-            uint32_t wlo[DB], whi[DB];
+            // bitmask words of this stage: units 128 kst .. 128 kst + 127
+            uint32_t wd[DB][kKStage / 2];
 #pragma unroll
-            for (int db = 0; db < DB; ++db) {
-                wlo[db] = myb[32 * db * WSTR + 2 * kst];
-                whi[db] = myb[32 * db * WSTR + 2 * kst + 1];
-            }
+            for (int db = 0; db < DB; ++db)
+#pragma unroll
+                for (int q = 0; q < kKStage / 2; ++q) wd[db][q] = myb[32 * db * WSTR + (kKStage / 2) * kst + q];
             if constexpr (PREC == RR_PREC_SPLIT_BF16) {
+                // Software pipeline: the B fragments of step kk + 1 are expanded between the
+                // MFMA groups of step kk (scheduling fences keep that order).
+                auto expand = [&](int kk, int db) {
+                    const uint32_t w = wd[db][kk >> 1];
+                    return __builtin_bit_cast(bf16x8, expand_bf16((w >> (16 * (kk & 1) + 8 * h)) & 0xFFu));
+                };
+                bf16x8 Bc[DB], Bn[DB];
+#pragma unroll
+                for (int db = 0; db < DB; ++db) Bc[db] = expand(0, db);
 #pragma unroll
                 for (int kk = 0; kk < kKStage; ++kk) {
-                    bf16x8 B[DB];
+                    const bool more = kk + 1 < kKStage;
+                    bf16x8 A[CB][2];
 #pragma unroll
-                    for (int db = 0; db < DB; ++db) {
-                        const uint32_t w = kk < 2 ? wlo[db] : whi[db];
-                        B[db] = __builtin_bit_cast(bf16x8, expand_bf16((w >> (16 * (kk & 1) + 8 * h)) & 0xFFu));
+                    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                        for (int p = 0; p < 2; ++p)
+                            A[cb][p] = __builtin_bit_cast(bf16x8, st[((kk * CB + cb) * 2 + p) * 64 + lane]);
+#pragma unroll
+                    for (int g = 0; g < 2 * CB; ++g) {
+                        const int cb = g >> 1, p = g & 1;
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int db = 0; db < DB; ++db)
+                            acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[cb][p], Bc[db], acc[cb][db], 0, 0, 0);
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (more && g < DB) Bn[g] = expand(kk + 1, g);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (more) {
 #pragma unroll
-                    for (int cb = 0; cb < CB; ++cb) {
-#pragma unroll
-                        for (int p = 0; p < 2; ++p) {
-                            const bf16x8 A = __builtin_bit_cast(bf16x8, st[((kk * CB + cb) * 2 + p) * 64 + lane]);
-#pragma unroll
-                            for (int db = 0; db < DB; ++db)
-                                acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B[db], acc[cb][db], 0, 0, 0);
-                        }
+                        for (int db = 0; db < DB; ++db) Bc[db] = Bn[db];
                     }
                 }
             } else {
@@ -149,7 +163,7 @@ void contract_kernel(ContractArgs a) {
                                 for (int q = 0; q < 4; ++q) {
 #pragma unroll
                                     for (int db = 0; db < DB; ++db) {
-                                        const uint32_t w = kk < 2 ? wlo[db] : whi[db];
+                                        const uint32_t w = wd[db][kk >> 1];
                                         const float bv = (float)((w >> (16 * (kk & 1) + 8 * p + 2 * q + h)) & 1u);
                                         stp[db] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[q], bv, stp[db], 0, 0, 0);
                                     }
@@ -162,22 +176,15 @@ void contract_kernel(ContractArgs a) {
                 }
             }
             if (kst == nst - 1) {
-                // ||G||^2 and sum_j |G_j| cabs_j over this chunk's covariates
+                // ||G||^2 over this chunk's covariates
 #pragma unroll
                 for (int db = 0; db < DB; ++db) {
-                    float s2 = 0.f, s1 = 0.f;
+                    float s2 = 0.f;
 #pragma unroll
-                    for (int cb = 0; cb < CB; ++cb) {
-                        const int cov0 = 32 * (chunk * CB + cb) + 4 * h;
+                    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const float g = acc[cb][db][r];
-                            s2 = fmaf(g, g, s2);
-                            s1 = fmaf(fabsf(g), a.cabs[cov0 + 8 * (r >> 2) + (r & 3)], s1);
-                        }
-                    }
+                        for (int r = 0; r < 16; ++r) s2 = fmaf(acc[cb][db][r], acc[cb][db][r], s2);
                     ss[db] += s2;
-                    sa[db] += s1;
                 }
             }
             __builtin_amdgcn_s_waitcnt(0);     // this wave's loads of the next stage landed
@@ -187,7 +194,8 @@ void contract_kernel(ContractArgs a) {
 #pragma unroll
         for (int db = 0; db < DB; ++db) {
             const float s2 = ss[db] + __shfl_xor(ss[db], 32, 64);
-            const float s1 = sa[db] + __shfl_xor(sa[db], 32, 64);
+            // sum_j |G_j| cabs_j <= ||G|| ||cabs|| (Cauchy-Schwarz); cnorm = ||cabs|| (1 + 2^-20)
+            const float s1 = sqrtf(s2) * (1.0f + 0x1p-20f) * a.cnorm;
             const uint64_t idx = tile0 + wave * 32 * DB + 32 * db + j;
             const bool live = h == 0 && idx < a.num;
             const float m32 = a.scale * s2;

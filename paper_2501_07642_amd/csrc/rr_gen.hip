@@ -12,7 +12,6 @@ namespace rr {
 
 template <int S, bool EXACT>
 __global__ __launch_bounds__(256) void gen_kernel(GenArgs g) {
-    __shared__ uint32_t shist[4][256];
     __shared__ uint2 slist[4][64];
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave, nw = (uint64_t)gridDim.x * 4;
@@ -30,7 +29,7 @@ __global__ __launch_bounds__(256) void gen_kernel(GenArgs g) {
     } else {
         for (uint64_t idx = gw; idx < g.num; idx += nw) {
             const uint64_t key = g.keylist ? g.keylist[idx] : g.key_begin + idx;
-            gen_mc_bits<S>(g.seed, key, g.n, g.n1, shist[wave], slist[wave], g.out + idx * (8 * S));
+            gen_mc_bits<S>(g.seed, key, g.n, g.n1, slist[wave], g.out + idx * (8 * S));
             __builtin_amdgcn_wave_barrier();
         }
     }
@@ -67,7 +66,6 @@ __global__ __launch_bounds__(256) void regen_kernel(const uint64_t* keys, uint64
                                                     int n, int n1, const uint64_t* binom,
                                                     uint32_t* out, int nw) {
     __shared__ uint32_t sbits[4][8 * kMaxS];
-    __shared__ uint32_t shist[4][256];
     __shared__ uint2 slist[4][64];
     const int wave = threadIdx.x >> 6, lane = lane_id();
     for (uint64_t k = (uint64_t)blockIdx.x * 4 + wave; k < K; k += (uint64_t)gridDim.x * 4) {
@@ -78,7 +76,7 @@ __global__ __launch_bounds__(256) void regen_kernel(const uint64_t* keys, uint64
                 sbits[wave][1] = (uint32_t)(m >> 32);
             }
         } else {
-            gen_mc_bits<S>(seed, keys[k], n, n1, shist[wave], slist[wave], sbits[wave]);
+            gen_mc_bits<S>(seed, keys[k], n, n1, slist[wave], sbits[wave]);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();

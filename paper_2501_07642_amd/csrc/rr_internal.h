@@ -30,6 +30,7 @@ void set_error(const std::string& msg);
 constexpr int kWave = 64;
 constexpr int kUnitsPerChunk = 256;   // one Philox block per lane yields 4 x 64 units
 constexpr int kKStep = 16;            // units per MFMA K step (32x32x16 BF16)
+constexpr int kKStepsPerStage = 8;    // K steps per LDS stage of the contraction
 constexpr int kColBlock = 32;         // covariates per MFMA row block
 constexpr int kRecordU4 = 128;        // uint4 per operand record: 2 planes x 64 lanes x 16 B
 constexpr int kMaxS = RR_MAX_N / kUnitsPerChunk;   // 16
@@ -41,7 +42,7 @@ struct Problem {
     double ridge_rel = 0, lambda = 0;
     int S = 0;             // 256-unit chunks per draw: ceil(n / 256)
     int wstride = 0;       // uint32 words per draw bitmask in the internal layout: 8 * S
-    int64_t ks = 0;        // K steps of 16 units, a multiple of 4 (units >= n are zero)
+    int64_t ks = 0;        // K steps of 16 units, a multiple of kKStepsPerStage (units >= n are zero)
     int64_t ncb = 0;       // covariate blocks of 32 (padded)
     double scale = 0;      // n / (n1 n0)
     // device buffers
@@ -80,6 +81,7 @@ struct ContractArgs {
     float scale;              // n / (n1 n0)
     float two_kappa;          // 2 * kappa: |G32_j - G_j| <= kappa * cabs_j
     float csq;                // kappa^2 * sum_j cabs_j^2
+    float cnorm;              // ||cabs||_2, rounded up
     float gamma_ss;           // relative bound of the FP32 sum of squares and the scaling
     float safety;             // multiplies the assembled bound
     const float* U;           // append iff lo <= *U; null appends every draw
@@ -165,21 +167,24 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // ---------------------------------------------------------------------------------------
 // Monte Carlo draw: the n1 units with the smallest (u_i, i) become treated.  Unit
 // i = 256 s + 64 r + lane reads word r of Philox block 64 s + lane under counter
-// (block, 0, lo32(key), hi32(key)) and the pool seed as Philox key.  The wave computes the
-// n1-th smallest pair exactly: a 256-bin histogram of the top byte (LDS atomics), then
-// narrower bytes while the selected bin still holds more than 64 values, then an explicit
-// ranking of the few values left, then index order among values equal to the threshold.
-// Output: bitmask words (bit i%32 of word i/32), written by lane 0 to `out` (8 S words).
+// (block, 0, lo32(key), hi32(key)) and the pool seed as Philox key.
 //
-// `hist` is a wave-private 256-word LDS array, `list` a wave-private 64-entry LDS array.
+// Selection (exact): the n1-th smallest value u* is bracketed by [lo, hi) with
+// #{u < lo} < n1 <= #{u < hi}; counts come from wave ballots.  Pivots interpolate inside
+// the bracket for the first steps (unit keys are uniform, so two or three steps leave a few
+// values), then bisect, so the loop ends after at most 4 + 32 steps for any input.  The
+// <= 64 values left in the bracket are ranked in LDS; values equal to u* are taken in unit
+// order.  Output: bitmask words (bit i%32 of word i/32), written by lane 0 to `out` (8 S
+// words).  `list` is a wave-private 64-entry LDS array.
 template <int S>
-__device__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint32_t* hist,
-                            uint2* list, uint32_t* out) {
+__device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint2* list,
+                                            uint32_t* out) {
     const int lane = lane_id();
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t blo = (uint32_t)key, bhi = (uint32_t)(key >> 32);
     const int chunks = (n + kUnitsPerChunk - 1) / kUnitsPerChunk;
     uint32_t u[S][4];
+    uint64_t vm[S][4];   // lanes holding a unit < n (wave-uniform)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         if (s < chunks) {
@@ -187,85 +192,69 @@ __device__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint32_t
             philox_block(c0, c1, c2, c3, k0, k1);
             u[s][0] = c0; u[s][1] = c1; u[s][2] = c2; u[s][3] = c3;
         } else {
-            u[s][0] = u[s][1] = u[s][2] = u[s][3] = 0xFFFFFFFFu;
+            u[s][0] = u[s][1] = u[s][2] = u[s][3] = 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int left = n - 256 * s - 64 * r;
+            vm[s][r] = left >= 64 ? ~0ull : (left <= 0 ? 0ull : ((1ull << left) - 1));
         }
     }
-    auto valid = [&](int s, int r) { return 256 * s + 64 * r + lane < n; };
+    auto count_below = [&](uint64_t p) -> int {   // #{valid u < p}, p in [0, 2^32]
+        if (p > 0xFFFFFFFFull) return n;
+        const uint32_t pv = (uint32_t)p;
+        int c = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (s < chunks) c += __builtin_popcountll(ballot(u[s][r] < pv) & vm[s][r]);
+        return c;
+    };
 
-    // Exact n1-th smallest value, byte by byte from the top.
-    uint32_t prefix = 0;     // bytes fixed so far (above `shift`)
-    int need = n1;           // rank (1-based) of the target among values matching prefix
-    int below = 0;           // valid values strictly below the current prefix range
-    int shift = 24;
-    int bin_count = 0;
-    for (;;) {
-        reinterpret_cast<uint4*>(hist)[lane] = make_uint4(0, 0, 0, 0);
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        const uint32_t hi_mask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            if (s < chunks) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (valid(s, r) && ((u[s][r] & hi_mask) == (prefix & hi_mask)))
-                        atomicAdd(&hist[(u[s][r] >> shift) & 255u], 1u);
-                }
-            }
+    uint64_t lo = 0, hi = 1ull << 32;
+    int clo = 0, chi = n;
+    // stop at <= 8 bracket values after a few cheap counts, at <= 64 after many
+    for (int it = 0; (chi - clo > 64 || (chi - clo > 8 && it < 6)) && hi - lo > 1; ++it) {
+        uint64_t p;
+        if (it < 4) {
+            const float f = (float)(n1 - clo) / (float)(chi - clo);
+            p = lo + (uint64_t)(f * (float)(hi - lo));
+        } else {
+            p = lo + ((hi - lo) >> 1);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const uint4 c = reinterpret_cast<const uint4*>(hist)[lane];
-        const uint32_t tot = c.x + c.y + c.z + c.w;
-        const uint32_t incl = wave_incl_scan(tot);
-        const uint32_t excl = incl - tot;
-        // bin j of this lane holds the target iff cum_before < need <= cum_before + cnt
-        int hit = -1;
-        uint32_t cb = 0, cnt = 0;
-        {
-            uint32_t run = excl;
-            const uint32_t cc[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (hit < 0 && run < (uint32_t)need && (uint32_t)need <= run + cc[j]) {
-                    hit = j; cb = run; cnt = cc[j];
-                }
-                run += cc[j];
-            }
+        p = p <= lo ? lo + 1 : (p >= hi ? hi - 1 : p);
+        const int c = count_below(p);
+        if (c < n1) {
+            lo = p;
+            clo = c;
+        } else {
+            hi = p;
+            chi = c;
         }
-        const uint64_t m = ballot(hit >= 0);
-        const int src = (int)__builtin_ctzll(m);
-        const int bin = __shfl(4 * lane + hit, src, 64);
-        const int cbs = (int)__shfl(cb, src, 64);
-        bin_count = (int)__shfl(cnt, src, 64);
-        below += cbs;
-        need -= cbs;
-        prefix |= (uint32_t)bin << shift;
-        if (bin_count <= 64 || shift == 0) break;
-        shift -= 8;
     }
 
-    // Threshold value ustar, count of valid values below it, how many equal ones to take.
     uint32_t ustar;
     int take, eq_total;
-    if (shift == 0) {
-        ustar = prefix;
-        take = need;
-        eq_total = bin_count;
-        // below already counts everything strictly below ustar
+    if (hi - lo == 1) {
+        // every value in the bracket equals lo
+        ustar = (uint32_t)lo;
+        take = n1 - clo;
+        eq_total = chi - clo;
     } else {
-        // Collect the <= 64 values of the selected bin into the list.
-        const uint32_t mask_hi = 0xFFFFFFFFu << shift;
+        // collect the <= 64 bracket values, rank them
+        const uint32_t l32 = (uint32_t)lo;
+        const uint64_t span = hi - lo;
         int base = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (s < chunks) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const bool f = valid(s, r) && ((u[s][r] & mask_hi) == prefix);
-                    const uint64_t bm = ballot(f);
+                    const bool f = (uint64_t)(u[s][r] - l32) < span;   // lo <= u < hi
+                    const uint64_t bm = ballot(f) & vm[s][r];
                     if (bm) {
-                        if (f) {
+                        if ((bm >> lane) & 1ull) {
                             const int pos = base + (int)__builtin_amdgcn_mbcnt_hi(
                                                        (uint32_t)(bm >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
@@ -278,20 +267,21 @@ __device__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint32_t
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        const int cnt = chi - clo;
+        const int need = n1 - clo;
         int lt = 0, le = 0;
-        const uint32_t mine = lane < bin_count ? list[lane].x : 0u;
-        for (int t = 0; t < bin_count; ++t) {
+        const uint32_t mine = lane < cnt ? list[lane].x : 0u;
+        for (int t = 0; t < cnt; ++t) {
             const uint32_t v = list[t].x;
             lt += v < mine;
             le += v <= mine;
         }
-        const bool is_t = lane < bin_count && lt < need && need <= le;
+        const bool is_t = lane < cnt && lt < need && need <= le;
         const uint64_t mt = ballot(is_t);
         const int src = (int)__builtin_ctzll(mt);
         ustar = __shfl(mine, src, 64);
         const int lts = __shfl(lt, src, 64);
         const int les = __shfl(le, src, 64);
-        below += lts;
         take = need - lts;
         eq_total = les - lts;
         __builtin_amdgcn_wave_barrier();
@@ -307,7 +297,7 @@ __device__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint32_t
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 if (!found && s < chunks) {
-                    uint64_t bm = ballot(valid(s, r) && u[s][r] == ustar);
+                    uint64_t bm = ballot(u[s][r] == ustar) & vm[s][r];
                     const int pc = __builtin_popcountll(bm);
                     if (left <= pc) {
                         for (int q = 1; q < left; ++q) bm &= bm - 1;
@@ -327,10 +317,15 @@ __device__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint32_t
         uint32_t w[8];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int unit = 256 * s + 64 * r + lane;
-            const bool t = s < chunks && valid(s, r) &&
-                           (u[s][r] < ustar || (u[s][r] == ustar && unit <= istar));
-            const uint64_t bm = ballot(t);
+            uint64_t bm = 0;
+            if (s < chunks) {
+                if (istar == 0x7FFFFFFF) {
+                    bm = ballot(u[s][r] <= ustar) & vm[s][r];
+                } else {
+                    const int unit = 256 * s + 64 * r + lane;
+                    bm = ballot(u[s][r] < ustar || (u[s][r] == ustar && unit <= istar)) & vm[s][r];
+                }
+            }
             w[2 * r] = (uint32_t)bm;
             w[2 * r + 1] = (uint32_t)(bm >> 32);
         }
@@ -339,7 +334,6 @@ __device__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint32_t
             reinterpret_cast<uint4*>(out + 8 * s)[1] = make_uint4(w[4], w[5], w[6], w[7]);
         }
     }
-    (void)below;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -244,7 +244,7 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     P.ridge_rel = ridge_rel;
     P.S = pow2_chunks((int)n);
     P.wstride = 8 * P.S;
-    P.ks = 4 * ((n + 4 * kKStep - 1) / (4 * kKStep));   // K steps, padded to whole LDS stages
+    P.ks = kKStepsPerStage * ((n + kKStepsPerStage * kKStep - 1) / (kKStepsPerStage * kKStep));  // whole LDS stages
     const int64_t cbq = 4;
     P.ncb = (((d + kColBlock - 1) / kColBlock + cbq - 1) / cbq) * cbq;
     P.scale = (double)n / ((double)n1 * (double)(n - n1));

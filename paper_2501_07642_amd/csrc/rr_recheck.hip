@@ -20,7 +20,6 @@ template <int S, bool EXACT>
 __global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a) {
     constexpr int WS = 8 * S + 1;
     __shared__ uint32_t bits[kRecheckTile][WS];
-    __shared__ uint32_t hist[4][256];
     __shared__ uint2 list[4][64];
     __shared__ double red[4][kRecheckTile];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -37,7 +36,7 @@ __global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a) {
                         bits[t][1] = (uint32_t)(m >> 32);
                     }
                 } else {
-                    gen_mc_bits<S>(a.seed, a.keys[e0 + t], a.n, a.n1, hist[wave], list[wave], bits[t]);
+                    gen_mc_bits<S>(a.seed, a.keys[e0 + t], a.n, a.n1, list[wave], bits[t]);
                 }
             } else {
                 for (int w = lane; w < 8 * S; w += 64) bits[t][w] = 0u;

@@ -34,6 +34,9 @@ int draw_cb(int prec, int S);
 
 
 constexpr double kEpsTie = 1e-10;
+// Generation workgroups per CU: three 4-wave workgroups (<= 80 VGPRs per wave) fit beside one
+// 8-wave contraction workgroup (128 VGPRs per wave, ~131 KB LDS) on every CU.
+constexpr int kGenWgPerCu = 3;
 constexpr double kQFuzz = 1e-12;
 
 // ---------------------------------------------------------------------------------------
@@ -475,9 +478,10 @@ static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint
 //          VALU (ks steps): gamma(16 + ks) sum|x32|, and |x - x32| <= 2^-24 |x|.
 // Hence |G32_j - G_j| <= kappa cabs_j with cabs_j = sum_i |X~_ij| >= the treated sum.  M32
 // errs by at most scale (2 kappa sum_j |G32_j| cabs_j + kappa^2 sum_j cabs_j^2) plus the
-// FP32 sum of squares (gamma(depth) M32); the assembled bound is multiplied by kSafety.
+// FP32 sum of squares (gamma(depth) M32); the kernel bounds sum_j |G32_j| cabs_j by
+// ||G32|| ||cabs|| (Cauchy-Schwarz), and the assembled bound is multiplied by kSafety.
 struct Bound {
-    float two_kappa, csq, gamma_ss, safety;
+    float two_kappa, csq, cnorm, gamma_ss, safety;
 };
 constexpr double kU = 0x1p-24;
 constexpr double kSafety = 1.25;
@@ -499,6 +503,7 @@ Bound bound_constants(const Problem& P, int prec, const std::vector<float>& cabs
     Bound b;
     b.two_kappa = (float)(2.0 * kappa * (1.0 + gamma_m(depth_ss)) * (1.0 + 1e-6));
     b.csq = (float)(kappa * kappa * c2 * 1.01);
+    b.cnorm = (float)(std::sqrt(c2) * (1.0 + 1e-6));
     b.gamma_ss = (float)(gamma_m(depth_ss) * 1.01);
     b.safety = (float)kSafety;
     return b;
@@ -530,6 +535,7 @@ static ContractArgs make_contract_args(const Problem& P, int prec, const Bound& 
     a.scale = (float)P.scale;
     a.two_kappa = b.two_kappa;
     a.csq = b.csq;
+    a.cnorm = b.cnorm;
     a.gamma_ss = b.gamma_ss;
     a.safety = b.safety;
     return a;
@@ -651,7 +657,7 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
         g.out = w.bits[bsel];
         RR_HIP(hipEventRecord(ev_t[4 * c + 2], P.gen_stream));
         const uint64_t gen_units = exact ? (num + 63) / 64 : num;
-        RR_HIP(launch_gen(P.S, exact, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * 2),
+        RR_HIP(launch_gen(P.S, exact, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * kGenWgPerCu),
                           P.gen_stream));
         RR_HIP(hipEventRecord(ev_t[4 * c + 3], P.gen_stream));
         RR_HIP(hipEventRecord(ev_ready[bsel], P.gen_stream));
@@ -878,7 +884,7 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
         g.out = bits;
         const int cus = device_cus(P.device);
         const uint64_t gen_units = exact ? (K + 63) / 64 : K;
-        hipError_t e = launch_gen(P.S, exact != 0, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * 2), st);
+        hipError_t e = launch_gen(P.S, exact != 0, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * kGenWgPerCu), st);
         ContractArgs a = make_contract_args(P, precision, b);
         a.bits = bits;
         a.num = K;
