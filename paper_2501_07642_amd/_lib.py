@@ -212,6 +212,8 @@ def rr_draw_balance_batched(problems, seeds, key_begin, num_draws, mode=MODE_QUA
     """Returns a list of (keys, M) per problem."""
     torch = _torch()
     npb = len(problems)
+    if npb == 0:
+        return []
     if capacity is None:
         capacity = quantile_count(q_or_a, num_draws) if mode == MODE_QUANTILE else num_draws
     dev = problems[0].device

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librr.so")
 ARCH = os.environ.get("RR_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["rr_prep.hip", "rr_gen.hip", "rr_contract.hip", "rr_recheck.hip", "rr_select.hip", "rr_frt.hip"]
+SOURCES = ["rr_prep.hip", "rr_gen.hip", "rr_contract.hip", "rr_recheck.hip", "rr_select.hip", "rr_frt.hip",
+           "rr_tune.hip", "rr_batch.hip"]
 
 
 def hipcc():
@@ -41,7 +42,7 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

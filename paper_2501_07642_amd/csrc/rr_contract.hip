@@ -41,9 +41,9 @@ __device__ __forceinline__ uint4 expand_bf16(uint32_t x) {
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
-template <int PREC, int NW, int CB, int DB, int S>
+template <int PREC, int NW, int CB, int DB, int S, bool BATCH>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 2)))
-void contract_kernel(ContractArgs a) {
+void contract_kernel(ContractArgs a0) {
     constexpr int TILE = NW * 32 * DB;
     constexpr int WSTR = 8 * S + 1;                       // +1: 32 draws hit 32 banks
     constexpr int REC = kKStage * CB * 2;                 // 1 KB plane records per stage
@@ -55,26 +55,30 @@ void contract_kernel(ContractArgs a) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, j = lane & 31;
-    const int nchunks = a.ncb / CB;
-    const int nst = a.ks / kKStage;          // ks is a multiple of kKStage
-    const int total = nchunks * nst;
-    const uint64_t ntiles = (a.num + TILE - 1) / TILE;
-
-    // Stage gs = (chunk, K stage) goes straight from global memory to LDS buffer `buf`;
-    // wave w moves plane records w, w + 4, ... (64 lanes x 16 B each).
-    auto issue_stage = [&](int gs, int buf) {
-        const int chunk = gs / nst, kst = gs % nst;
-#pragma unroll
-        for (int r = wave; r < REC; r += NW) {
-            const int kk = r / (CB * 2), cb = (r >> 1) % CB, p = r & 1;
-            const int k = kst * kKStage + kk;     // ks is a multiple of kKStage
-            const uint4* src = a.op + ((size_t)k * a.ncb + chunk * CB + cb) * kRecordU4 + 64 * p + lane;
-            __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(sA + buf * STAGE_U4 + r * 64), 16, 0, 0);
-        }
-    };
+    // Batched launches walk the (problem, tile) list of all pools; the list is ordered
+    // longest problem first, so the grid-stride assignment balances uneven problems.
+    const uint64_t ntiles = BATCH ? (uint64_t)a0.nprob * a0.tpp : (a0.num + TILE - 1) / TILE;
 
     for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const uint64_t tile0 = t * TILE;
+        const ContractArgs& a = BATCH ? a0.tab[t / a0.tpp] : a0;
+        const uint64_t tile0 = (BATCH ? t % a0.tpp : t) * TILE;
+        const int nchunks = a.ncb / CB;
+        const int nst = a.ks / kKStage;          // ks is a multiple of kKStage
+        const int total = nchunks * nst;
+
+        // Stage gs = (chunk, K stage) goes straight from global memory to LDS buffer `buf`;
+        // wave w moves plane records w, w + NW, ... (64 lanes x 16 B each).
+        auto issue_stage = [&](int gs, int buf) {
+            const int chunk = gs / nst, kst = gs % nst;
+#pragma unroll
+            for (int r = wave; r < REC; r += NW) {
+                const int kk = r / (CB * 2), cb = (r >> 1) % CB, p = r & 1;
+                const int k = kst * kKStage + kk;
+                const uint4* src = a.op + ((size_t)k * a.ncb + chunk * CB + cb) * kRecordU4 + 64 * p + lane;
+                __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(sA + buf * STAGE_U4 + r * 64), 16, 0, 0);
+            }
+        };
+        if (tile0 >= a.num) continue;
         for (int e = tid; e < TILE * 8 * S; e += NW * 64) {
             const int dr = e / (8 * S), w = e % (8 * S);
             const uint64_t idx = tile0 + dr;
@@ -200,14 +204,20 @@ void contract_kernel(ContractArgs a) {
             const bool live = h == 0 && idx < a.num;
             const float m32 = a.scale * s2;
             const float err = a.safety * (a.scale * (a.two_kappa * s1 + a.csq) + a.gamma_ss * m32);
-            if (a.out_m32) {
+            const float hi = (m32 + err) * (1.0f + 0x1p-21f);
+            const float lo = fmaxf((m32 - err) * (1.0f - 0x1p-21f), 0.0f);
+            if (a.out_err) {
                 if (live) {
                     a.out_m32[idx] = m32;
                     a.out_err[idx] = err;
                 }
+            } else if (a.out_hi) {
+                if (live) {
+                    a.out_hi[idx] = hi;
+                    a.out_lo[idx] = lo;
+                    a.out_m32[idx] = m32;
+                }
             } else {
-                const float hi = (m32 + err) * (1.0f + 0x1p-21f);
-                const float lo = fmaxf((m32 - err) * (1.0f - 0x1p-21f), 0.0f);
                 const bool pass = live && (a.U == nullptr || lo <= *a.U);
                 const uint64_t bm = __ballot(pass);
                 if (bm) {
@@ -231,50 +241,75 @@ void contract_kernel(ContractArgs a) {
     }
 }
 
-// Tile shapes: covariate blocks per chunk (CB) and 32-draw blocks per wave (DB).
-// Tile shapes.  Split BF16: 8 waves (two per SIMD, so one wave's bit expansion on the
-// VALU overlaps the other's MFMA), each with 2 x DB accumulator blocks of 32x32 (<= 128
-// registers, leaving room for the generation kernel's waves); FP32: 4 waves of 2 x DB blocks
-// plus a per-K-step block set.  Fewer draws per wave for long bitmasks (LDS).
+// Tile shapes: covariate blocks per chunk (CB) and 32-draw blocks per wave (DB).  Split
+// BF16: 8 waves (two per SIMD, so one wave's bit expansion on the VALU overlaps the other's
+// MFMA), each with 2 x DB accumulator blocks of 32x32 (<= 128 registers, leaving room for
+// the generation kernel's waves); FP32: 4 waves of 2 x DB blocks plus a per-K-step block
+// set.  The default DB is 2 where the tile's bitmasks fit in LDS beside the operand stages;
+// the autotuner may pick 1.  Per-draw arithmetic (and so every M32) does not depend on NW
+// or DB, only on CB.
+constexpr int kCB = 2;
 constexpr int nw_for(int prec, int S) { return prec == RR_PREC_SPLIT_BF16 && S <= 8 ? 8 : 4; }
-constexpr int cb_for(int, int) { return 2; }
-constexpr int db_for(int prec, int S) { return prec == RR_PREC_SPLIT_BF16 ? (S <= 4 ? 2 : 1) : (S <= 8 ? 2 : 1); }
-
-template <int PREC, int S>
-static size_t contract_lds() {
-    return sizeof(uint4) * 2 * kKStage * cb_for(PREC, S) * kRecordU4 +
-           sizeof(uint32_t) * (nw_for(PREC, S) * 32 * db_for(PREC, S)) * (8 * S + 1);
+constexpr size_t lds_for(int prec, int S, int db) {
+    return sizeof(uint4) * 2 * kKStage * kCB * kRecordU4 + sizeof(uint32_t) * (nw_for(prec, S) * 32 * db) * (8 * S + 1);
+}
+constexpr size_t kMaxLds = 160 * 1024;
+constexpr int db_default(int prec, int S) {
+    return prec == RR_PREC_SPLIT_BF16 ? (S <= 4 ? 2 : 1) : (S <= 8 ? 2 : 1);
 }
 
-template <int PREC, int S>
+template <int PREC, int S, int DB, bool BATCH>
 static hipError_t launch_contract_t(const ContractArgs& a, int grid, hipStream_t st) {
-    auto k = contract_kernel<PREC, nw_for(PREC, S), cb_for(PREC, S), db_for(PREC, S), S>;
-    const size_t lds = contract_lds<PREC, S>();
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * nw_for(PREC, S)), lds, st, a);
-    return hipGetLastError();
+    if constexpr (lds_for(PREC, S, DB) > kMaxLds) {
+        return hipErrorInvalidConfiguration;
+    } else {
+        auto k = contract_kernel<PREC, nw_for(PREC, S), kCB, DB, S, BATCH>;
+        const size_t lds = lds_for(PREC, S, DB);
+        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(64 * nw_for(PREC, S)), lds, st, a);
+        return hipGetLastError();
+    }
 }
 
-template <int PREC>
-static hipError_t launch_contract_p(int S, const ContractArgs& a, int grid, hipStream_t st) {
+template <int PREC, bool BATCH>
+static hipError_t launch_contract_p(int S, int db, const ContractArgs& a, int grid, hipStream_t st) {
+#define RR_CASE(SV)                                                                       \
+    case SV:                                                                              \
+        return db == 1 ? launch_contract_t<PREC, SV, 1, BATCH>(a, grid, st)               \
+                       : launch_contract_t<PREC, SV, 2, BATCH>(a, grid, st);
     switch (S) {
-        case 1: return launch_contract_t<PREC, 1>(a, grid, st);
-        case 2: return launch_contract_t<PREC, 2>(a, grid, st);
-        case 4: return launch_contract_t<PREC, 4>(a, grid, st);
-        case 8: return launch_contract_t<PREC, 8>(a, grid, st);
-        case 16: return launch_contract_t<PREC, 16>(a, grid, st);
+        RR_CASE(1)
+        RR_CASE(2)
+        RR_CASE(4)
+        RR_CASE(8)
+        RR_CASE(16)
     }
+#undef RR_CASE
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_contract(int S, int prec, const ContractArgs& a, int grid, hipStream_t st) {
+bool contract_db_ok(int prec, int S, int db) {
+    return (db == 1 || db == 2) && lds_for(prec, S, db) <= kMaxLds;
+}
+int contract_db_default(int prec, int S) { return db_default(prec, S); }
+
+// db = 0 selects the default tile.  Batched launches take the problem table from a.tab.
+hipError_t launch_contract(int S, int prec, int db, bool batch, const ContractArgs& a, int grid, hipStream_t st) {
     grid = std::max(1, grid);
-    return prec == RR_PREC_SPLIT_BF16 ? launch_contract_p<RR_PREC_SPLIT_BF16>(S, a, grid, st)
-                                      : launch_contract_p<RR_PREC_FP32>(S, a, grid, st);
+    if (db == 0) db = db_default(prec, S);
+    if (!contract_db_ok(prec, S, db)) return hipErrorInvalidConfiguration;
+    if (prec == RR_PREC_SPLIT_BF16)
+        return batch ? launch_contract_p<RR_PREC_SPLIT_BF16, true>(S, db, a, grid, st)
+                     : launch_contract_p<RR_PREC_SPLIT_BF16, false>(S, db, a, grid, st);
+    return batch ? launch_contract_p<RR_PREC_FP32, true>(S, db, a, grid, st)
+                 : launch_contract_p<RR_PREC_FP32, false>(S, db, a, grid, st);
 }
 
-int contract_tile(int prec, int S) { return nw_for(prec, S) * 32 * db_for(prec, S); }
-int draw_cb(int prec, int S) { return cb_for(prec, S); }
+int contract_tile(int prec, int S, int db) {
+    if (db == 0) db = db_default(prec, S);
+    return nw_for(prec, S) * 32 * db;
+}
+int draw_cb(int, int) { return kCB; }
 
 }  // namespace rr

@@ -52,6 +52,35 @@ hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t
     return hipGetLastError();
 }
 
+// Batched generation over a table of pools: global draw index idx belongs to pool
+// idx / per (draw idx % per of the pool's range).  One wave per draw.
+template <int S>
+__global__ __launch_bounds__(256) void gen_batch_kernel(const GenArgs* tab, uint64_t total, uint64_t per) {
+    __shared__ uint2 slist[4][64];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave, nw = (uint64_t)gridDim.x * 4;
+    for (uint64_t idx = gw; idx < total; idx += nw) {
+        const uint64_t p = idx / per, i = idx - p * per;
+        const GenArgs& g = tab[p];
+        gen_mc_bits<S>(g.seed, g.key_begin + i, g.n, g.n1, slist[wave], g.out + i * (8 * S));
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+hipError_t launch_gen_batch(int S, const GenArgs* tab, uint64_t nprob, uint64_t per, int grid, hipStream_t st) {
+    grid = std::max(1, grid);
+    const uint64_t total = nprob * per;
+    switch (S) {
+        case 1: hipLaunchKernelGGL((gen_batch_kernel<1>), dim3(grid), dim3(256), 0, st, tab, total, per); break;
+        case 2: hipLaunchKernelGGL((gen_batch_kernel<2>), dim3(grid), dim3(256), 0, st, tab, total, per); break;
+        case 4: hipLaunchKernelGGL((gen_batch_kernel<4>), dim3(grid), dim3(256), 0, st, tab, total, per); break;
+        case 8: hipLaunchKernelGGL((gen_batch_kernel<8>), dim3(grid), dim3(256), 0, st, tab, total, per); break;
+        case 16: hipLaunchKernelGGL((gen_batch_kernel<16>), dim3(grid), dim3(256), 0, st, tab, total, per); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 int pow2_chunks(int n) {
     int c = (n + kUnitsPerChunk - 1) / kUnitsPerChunk;
     int S = 1;

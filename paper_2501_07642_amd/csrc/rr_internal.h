@@ -52,12 +52,15 @@ struct Problem {
     uint4* op_split = nullptr; // ks * ncb records: BF16 hi / lo planes
     uint4* op_f32 = nullptr;   // ks * ncb records: FP32 planes
     float* cabs = nullptr;     // 32 * ncb column sums of |X~| (rounded up; 0 for pads)
+    double cabs_c2 = 0;        // sum of cabs^2 (host copy, for the error bound)
     // workspace for the draw pipeline (grown on demand)
     void* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t gen_stream = nullptr;     // internal stream of the generation kernels
     std::vector<hipEvent_t> events;       // chunk ordering and timing
+    struct BatchState* batch = nullptr;   // batched-call resources when this handle leads a batch
 };
+void free_batch_state(Problem& P);
 
 
 // ---------------------------------------------------------------------------------------
@@ -91,8 +94,13 @@ struct ContractArgs {
     float* cand_m;
     uint32_t* cand_count;
     uint32_t cand_cap;
-    float* out_m32;           // evaluation mode (non-null): per-draw outputs, no prefilter
-    float* out_err;
+    float* out_m32;           // evaluation mode (with out_err) or dense mode (with out_hi / out_lo)
+    float* out_err;           // evaluation mode: per-draw m32 and error bound, no prefilter
+    float* out_hi;            // dense mode: per-draw upper / lower bounds and m32 at index i
+    float* out_lo;
+    // batched launches: tile t covers draws of problem tab[t / tpp], tile t % tpp
+    const ContractArgs* tab;
+    uint32_t tpp, nprob;
 };
 
 struct RecheckArgs {
@@ -106,11 +114,64 @@ struct RecheckArgs {
     double* out;              // M64 per entry
 };
 
+// Launch configuration of the draw pipeline, chosen by the autotuner per problem bucket:
+// draws per wave block of the contraction tile (db, 1 or 2) and generation workgroups per CU.
+struct Tune {
+    int db;
+    int gen_wg;
+};
+// Generation workgroups per CU by default: three 4-wave workgroups (<= 80 VGPRs per wave) fit
+// beside one 8-wave contraction workgroup (128 VGPRs per wave, up to ~131 KB LDS) on every CU.
+constexpr int kGenWgPerCu = 3;
+
+// Rigorous error-bound constants of the FP32 contraction of a problem (see rr_select.hip).
+struct Bound {
+    float two_kappa, csq, cnorm, gamma_ss, safety;
+};
+
+// Acceptance bookkeeping of one pool (device).
+struct AcceptState {
+    uint32_t k;               // quantile mode: accepted count
+    uint32_t nL;              // accepted outright (FP32 bounds below the boundary)
+    uint32_t band_count;      // guard-band entries
+    uint32_t acc_count;       // accepted entries written
+    uint32_t guard_fail;      // band selection inconsistent
+    uint32_t overflow;        // a list exceeded its capacity
+    uint32_t done;            // batched pools: sorted outputs written on the device
+};
+
 }  // namespace rr
 
 struct rr_problem {
     rr::Problem P;
 };
+
+namespace rr {
+// Host functions shared by the translation units.
+hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t st);
+hipError_t launch_gen_batch(int S, const GenArgs* tab, uint64_t nprob, uint64_t per, int grid, hipStream_t st);
+hipError_t launch_contract(int S, int prec, int db, bool batch, const ContractArgs& a, int grid, hipStream_t st);
+int contract_tile(int prec, int S, int db);
+bool contract_db_ok(int prec, int S, int db);
+int contract_db_default(int prec, int S);
+int draw_cb(int prec, int S);
+hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hipStream_t st);
+hipError_t launch_recheck_batch(int S, const RecheckArgs* tab, int nprob, int gx, hipStream_t st);
+int pow2_chunks(int n);
+int device_cus(int dev);
+const uint64_t* binom_table(int dev);
+Bound bound_constants(const Problem& P, int prec);
+ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b);
+Tune tune_default(int prec, int S);
+Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t st);
+rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begin, uint64_t N, int mode,
+                        double q_or_a, int prec, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
+                        uint64_t capacity, uint64_t* h_count, hipStream_t st, const Tune* tune);
+hipError_t sort_accepted(const uint64_t* acc_key, const double* acc_m, const uint8_t* acc_flag, uint32_t n,
+                         uint64_t* const sk[2], uint32_t* const si[2], uint64_t* out_key, double* out_m,
+                         uint8_t* out_flag, hipStream_t st);
+void set_timing(double total_ms, double contract_ms, double gen_ms, int64_t launches, uint64_t band);
+}  // namespace rr
 
 namespace rr {
 

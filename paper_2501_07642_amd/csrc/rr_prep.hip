@@ -245,7 +245,7 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     P.S = pow2_chunks((int)n);
     P.wstride = 8 * P.S;
     P.ks = kKStepsPerStage * ((n + kKStepsPerStage * kKStep - 1) / (kKStepsPerStage * kKStep));  // whole LDS stages
-    const int64_t cbq = 4;
+    const int64_t cbq = 2;   // covariate blocks per contraction chunk
     P.ncb = (((d + kColBlock - 1) / kColBlock + cbq - 1) / cbq) * cbq;
     P.scale = (double)n / ((double)n1 * (double)(n - n1));
     const int64_t dpad = 32 * P.ncb;
@@ -329,7 +329,14 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     hipLaunchKernelGGL(cabs_kernel, dim3((unsigned)((dpad + 255) / 256)), dim3(256), 0, st, P.X64, n, d, dpad,
                        P.cabs);
     RR_PHIP(hipGetLastError());
-    RR_PHIP(hipStreamSynchronize(st));
+    {
+        std::vector<float> hc((size_t)dpad);
+        RR_PHIP(hipMemcpyAsync(hc.data(), P.cabs, sizeof(float) * dpad, hipMemcpyDeviceToHost, st));
+        RR_PHIP(hipStreamSynchronize(st));
+        double c2 = 0.0;
+        for (float c : hc) c2 += (double)c * (double)c;
+        P.cabs_c2 = c2;
+    }
     hipFree(S);
     hipFree(piv);
     hipFree(scal);

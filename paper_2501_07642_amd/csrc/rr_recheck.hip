@@ -16,15 +16,16 @@ namespace rr {
 // fixed order.
 constexpr int kRecheckTile = 16;
 
+// Workgroup wg of nwg takes the entry tiles wg, wg + nwg, ...
 template <int S, bool EXACT>
-__global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a) {
+__device__ __forceinline__ void recheck_run(const RecheckArgs& a, uint32_t wg, uint32_t nwg) {
     constexpr int WS = 8 * S + 1;
     __shared__ uint32_t bits[kRecheckTile][WS];
     __shared__ uint2 list[4][64];
     __shared__ double red[4][kRecheckTile];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint32_t cnt = *a.count;
-    for (uint32_t e0 = blockIdx.x * kRecheckTile; e0 < cnt; e0 += gridDim.x * kRecheckTile) {
+    for (uint32_t e0 = wg * kRecheckTile; e0 < cnt; e0 += nwg * kRecheckTile) {
         const int nt = (int)min<uint32_t>(kRecheckTile, cnt - e0);
         for (int t = wave; t < kRecheckTile; t += 4) {
             if (t < nt) {
@@ -84,6 +85,30 @@ __global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a) {
         if (tid < nt) a.out[e0 + tid] = a.scale * ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
         __syncthreads();
     }
+}
+
+template <int S, bool EXACT>
+__global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a) {
+    recheck_run<S, EXACT>(a, blockIdx.x, gridDim.x);
+}
+
+// Batched: pool tab[blockIdx.y], its entries strided over blockIdx.x.
+template <int S>
+__global__ __launch_bounds__(256) void recheck_batch_kernel(const RecheckArgs* tab) {
+    recheck_run<S, false>(tab[blockIdx.y], blockIdx.x, gridDim.x);
+}
+
+hipError_t launch_recheck_batch(int S, const RecheckArgs* tab, int nprob, int gx, hipStream_t st) {
+    const dim3 grid((unsigned)std::max(1, gx), (unsigned)nprob);
+    switch (S) {
+        case 1: hipLaunchKernelGGL((recheck_batch_kernel<1>), grid, dim3(256), 0, st, tab); break;
+        case 2: hipLaunchKernelGGL((recheck_batch_kernel<2>), grid, dim3(256), 0, st, tab); break;
+        case 4: hipLaunchKernelGGL((recheck_batch_kernel<4>), grid, dim3(256), 0, st, tab); break;
+        case 8: hipLaunchKernelGGL((recheck_batch_kernel<8>), grid, dim3(256), 0, st, tab); break;
+        case 16: hipLaunchKernelGGL((recheck_batch_kernel<16>), grid, dim3(256), 0, st, tab); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hipStream_t st) {

@@ -20,24 +20,14 @@
 #include <cstring>
 #include <mutex>
 
+#include "rr_accept.h"
 #include "rr_internal.h"
 
 namespace rr {
 
-hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t st);
-hipError_t launch_contract(int S, int prec, const ContractArgs& a, int grid, hipStream_t st);
-int contract_tile(int prec, int S);
-hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hipStream_t st);
+const uint64_t* binom_table_ext(int dev);
 hipError_t launch_regen(int S, bool exact, const uint64_t* keys, uint64_t K, uint64_t seed, int n, int n1,
                         const uint64_t* binom, uint32_t* out, int nw, int grid, hipStream_t st);
-int draw_cb(int prec, int S);
-
-
-constexpr double kEpsTie = 1e-10;
-// Generation workgroups per CU: three 4-wave workgroups (<= 80 VGPRs per wave) fit beside one
-// 8-wave contraction workgroup (128 VGPRs per wave, ~131 KB LDS) on every CU.
-constexpr int kGenWgPerCu = 3;
-constexpr double kQFuzz = 1e-12;
 
 // ---------------------------------------------------------------------------------------
 // Error state and timing.
@@ -50,6 +40,13 @@ struct Timing {
     uint64_t band = 0;
 };
 static thread_local Timing g_timing;
+void set_timing(double total_ms, double contract_ms, double gen_ms, int64_t launches, uint64_t band) {
+    g_timing.total_ms = total_ms;
+    g_timing.contract_ms = contract_ms;
+    g_timing.gen_ms = gen_ms;
+    g_timing.launches = launches;
+    g_timing.band = band;
+}
 
 // ---------------------------------------------------------------------------------------
 // Device control block.
@@ -60,11 +57,7 @@ struct Ctl {
     uint32_t sel_prefix[2];
     uint32_t sel_krem[2];
     uint32_t sel_fail;
-    uint32_t k;
-    uint32_t nL;          // accepted outright (written into the accepted list)
-    uint32_t band_count;
-    uint32_t acc_count;
-    uint32_t guard_fail;
+    AcceptState ac;
     uint32_t hist[2][256];
 };
 
@@ -132,30 +125,14 @@ __global__ void sel_scan_kernel(Ctl* ctl, int shift) {
     // one wave per selection
     const int s = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t need = ctl->sel_krem[s];
-    const uint4 c = reinterpret_cast<const uint4*>(ctl->hist[s])[lane];
-    const uint32_t tot = c.x + c.y + c.z + c.w;
-    const uint32_t incl = wave_incl_scan(tot);
-    uint32_t run = incl - tot;
-    const uint32_t cc[4] = {c.x, c.y, c.z, c.w};
-    int hit = -1;
-    uint32_t cb = 0;
-    for (int j = 0; j < 4; ++j) {
-        if (hit < 0 && run < need && need <= run + cc[j]) {
-            hit = j;
-            cb = run;
-        }
-        run += cc[j];
-    }
-    const uint64_t m = __ballot(hit >= 0);
-    if (m == 0) {
-        if (lane == 0) ctl->sel_fail = 1;
-    } else {
-        const int src = (int)__builtin_ctzll(m);
-        const int bin = __shfl(4 * lane + hit, src, 64);
-        const uint32_t cbs = __shfl(cb, src, 64);
-        if (lane == 0) {
-            ctl->sel_prefix[s] |= (uint32_t)bin << shift;
-            ctl->sel_krem[s] = need - cbs;
+    uint32_t bin, below;
+    const bool ok = wave_digit_select(ctl->hist[s], need, &bin, &below);
+    if (lane == 0) {
+        if (!ok) {
+            ctl->sel_fail = 1;
+        } else {
+            ctl->sel_prefix[s] |= bin << shift;
+            ctl->sel_krem[s] = need - below;
         }
     }
     reinterpret_cast<uint4*>(ctl->hist[s])[lane] = make_uint4(0, 0, 0, 0);
@@ -163,7 +140,7 @@ __global__ void sel_scan_kernel(Ctl* ctl, int shift) {
 
 __global__ void sel_init_kernel(Ctl* ctl) {
     ctl->sel_prefix[0] = ctl->sel_prefix[1] = 0;
-    ctl->sel_krem[0] = ctl->sel_krem[1] = ctl->k;
+    ctl->sel_krem[0] = ctl->sel_krem[1] = ctl->ac.k;
 }
 
 __device__ __forceinline__ float f32_up(double x) {
@@ -184,132 +161,42 @@ __global__ void classify_kernel(const uint64_t* ck, const float* chi, const floa
                                 uint8_t* acc_flag, uint32_t acc_cap, uint64_t* band_key,
                                 uint32_t band_cap) {
     const uint32_t n = ctl->cand_count;
-    double lo_cut, hi_cut;
+    double lo_cut = 0.0, hi_cut = 0.0;
     if (mode == RR_MODE_QUANTILE) {
         lo_cut = (double)__uint_as_float(ctl->sel_prefix[1]) * (1.0 - kEpsTie);
         hi_cut = (double)__uint_as_float(ctl->sel_prefix[0]) * (1.0 + kEpsTie);
     }
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const double hi = chi[i], lo = clo[i];
         bool acc, band;
-        if (mode == RR_MODE_QUANTILE) {
-            acc = hi < lo_cut;
-            band = !acc && lo <= hi_cut && hi >= lo_cut;
-        } else {
-            acc = hi <= a;
-            band = !acc && lo <= a;
-        }
+        classify_one(chi[i], clo[i], mode, a, lo_cut, hi_cut, &acc, &band);
         if (acc) {
-            const uint32_t p = atomicAdd(&ctl->acc_count, 1u);
-            atomicAdd(&ctl->nL, 1u);
+            const uint32_t p = atomicAdd(&ctl->ac.acc_count, 1u);
+            atomicAdd(&ctl->ac.nL, 1u);
             if (p < acc_cap) {
                 acc_key[p] = ck[i];
                 acc_m[p] = (double)cm[i];
                 acc_flag[p] = 0;
             }
         } else if (band) {
-            const uint32_t p = atomicAdd(&ctl->band_count, 1u);
+            const uint32_t p = atomicAdd(&ctl->ac.band_count, 1u);
             if (p < band_cap) band_key[p] = ck[i];
         }
     }
 }
 
 __global__ void cap_band_kernel(Ctl* ctl, uint32_t cap) {
-    if (ctl->band_count > cap) {
+    if (ctl->ac.band_count > cap) {
         ctl->overflow = 1;
-        ctl->band_count = cap;
+        ctl->ac.band_count = cap;
     }
 }
 
-// Single-workgroup selection among the guard band (FP64 values) and final acceptance.
-__device__ uint64_t block_select_u64(const uint64_t* v, const uint8_t* ok, uint32_t n, uint32_t k,
-                                     uint32_t* hist) {
-    // k-th smallest (1-based) of v[i] over i with ok[i] (ok null = all)
-    uint64_t prefix = 0;
-    for (int shift = 56; shift >= 0; shift -= 8) {
-        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
-        __syncthreads();
-        const uint64_t m = shift == 56 ? 0ull : (~0ull << (shift + 8));
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            if (ok && !ok[i]) continue;
-            const uint64_t x = v[i];
-            if ((x & m) == (prefix & m)) atomicAdd(&hist[(x >> shift) & 255u], 1u);
-        }
-        __syncthreads();
-        __shared__ uint32_t s_bin, s_below;
-        if (threadIdx.x == 0) {
-            uint32_t run = 0;
-            int bin = 255;
-            for (int b = 0; b < 256; ++b) {
-                if (run + hist[b] >= k) {
-                    bin = b;
-                    break;
-                }
-                run += hist[b];
-            }
-            s_bin = (uint32_t)bin;
-            s_below = run;
-        }
-        __syncthreads();
-        prefix |= (uint64_t)s_bin << shift;
-        k -= s_below;
-        __syncthreads();
-    }
-    return prefix;
-}
-
+// Single-workgroup final acceptance among the guard band.
 __global__ __launch_bounds__(1024) void band_accept_kernel(const uint64_t* bkey, const double* bm, uint8_t* work,
                                                            Ctl* ctl, int mode, double a, uint64_t* acc_key,
                                                            double* acc_m, uint8_t* acc_flag, uint32_t acc_cap) {
     __shared__ uint32_t hist[256];
-    __shared__ uint32_t s_cnt;
-    const uint32_t nb = ctl->band_count;
-    if (mode == RR_MODE_THRESHOLD) {
-        for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
-            if (bm[i] <= a) {
-                const uint32_t p = atomicAdd(&ctl->acc_count, 1u);
-                if (p < acc_cap) {
-                    acc_key[p] = bkey[i];
-                    acc_m[p] = bm[i];
-                    acc_flag[p] = 1;
-                }
-            }
-        }
-        return;
-    }
-    const int64_t need = (int64_t)ctl->k - (int64_t)ctl->nL;
-    if (need < 1 || (int64_t)nb < need) {
-        if (threadIdx.x == 0) ctl->guard_fail = 1;
-        return;
-    }
-    const uint64_t* bits = reinterpret_cast<const uint64_t*>(bm);
-    const double t = __longlong_as_double((long long)block_select_u64(bits, nullptr, nb, (uint32_t)need, hist));
-    const double lo_cut = t * (1.0 - kEpsTie), tol = kEpsTie * t;
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
-        const bool low = bm[i] < lo_cut;
-        const bool near = fabs(bm[i] - t) <= tol;
-        work[i] = near ? 1 : 0;
-        if (low) atomicAdd(&s_cnt, 1u);
-    }
-    __syncthreads();
-    const int64_t take = need - (int64_t)s_cnt;
-    uint64_t kstar = 0;
-    if (take >= 1) kstar = block_select_u64(bkey, work, nb, (uint32_t)take, hist);
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) {
-        const bool low = bm[i] < lo_cut;
-        const bool pick = low || (work[i] && take >= 1 && bkey[i] <= kstar);
-        if (pick) {
-            const uint32_t p = atomicAdd(&ctl->acc_count, 1u);
-            if (p < acc_cap) {
-                acc_key[p] = bkey[i];
-                acc_m[p] = bm[i];
-                acc_flag[p] = 1;
-            }
-        }
-    }
+    band_accept_block(bkey, bm, work, &ctl->ac, mode, a, acc_key, acc_m, acc_flag, acc_cap, hist);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -329,25 +216,7 @@ __global__ __launch_bounds__(1024) void sort_chunk_kernel(const uint64_t* key, u
         si[i] = g < n ? g : 0xFFFFFFFFu;
     }
     __syncthreads();
-    for (int size = 2; size <= kSortChunk; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < kSortChunk / 2; t += blockDim.x) {
-                const int i = 2 * t - (t & (stride - 1));
-                const int jx = i + stride;
-                const bool up = ((i & size) == 0);
-                const uint64_t ki = sk[i], kj = sk[jx];
-                const uint32_t ii = si[i], ij = si[jx];
-                const bool swap = up ? (ki > kj || (ki == kj && ii > ij)) : (ki < kj || (ki == kj && ii < ij));
-                if (swap) {
-                    sk[i] = kj;
-                    sk[jx] = ki;
-                    si[i] = ij;
-                    si[jx] = ii;
-                }
-            }
-            __syncthreads();
-        }
-    }
+    bitonic_sort_lds<kSortChunk>(sk, si);
     for (int i = threadIdx.x; i < kSortChunk; i += blockDim.x) {
         const uint32_t g = base + i;
         if (g < n) {
@@ -393,7 +262,26 @@ __global__ void gather_out_kernel(const uint64_t* sk, const uint32_t* si, uint32
     if (g >= n) return;
     okey[g] = sk[g];
     om[g] = m[si[g]];
-    if (of) of[g] = f[si[g]];
+    if (of && f) of[g] = f[si[g]];
+}
+
+// Accepted (key, M, flag) triples sorted by key into the outputs; sk / si are two scratch
+// buffers of n entries each.
+hipError_t sort_accepted(const uint64_t* acc_key, const double* acc_m, const uint8_t* acc_flag, uint32_t n,
+                         uint64_t* const sk[2], uint32_t* const si[2], uint64_t* out_key, double* out_m,
+                         uint8_t* out_flag, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const uint32_t chunks = (n + kSortChunk - 1) / kSortChunk;
+    hipLaunchKernelGGL(sort_chunk_kernel, dim3(chunks), dim3(1024), 0, st, acc_key, n, sk[0], si[0]);
+    int cur = 0;
+    for (uint32_t width = kSortChunk; width < n; width *= 2) {
+        hipLaunchKernelGGL(merge_pass_kernel, dim3((n + 255) / 256), dim3(256), 0, st, sk[cur], si[cur], n, width,
+                           sk[cur ^ 1], si[cur ^ 1]);
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(gather_out_kernel, dim3((n + 255) / 256), dim3(256), 0, st, sk[cur], si[cur], n, acc_m,
+                       acc_flag, out_key, out_m, out_flag);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
@@ -480,23 +368,19 @@ static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint
 // errs by at most scale (2 kappa sum_j |G32_j| cabs_j + kappa^2 sum_j cabs_j^2) plus the
 // FP32 sum of squares (gamma(depth) M32); the kernel bounds sum_j |G32_j| cabs_j by
 // ||G32|| ||cabs|| (Cauchy-Schwarz), and the assembled bound is multiplied by kSafety.
-struct Bound {
-    float two_kappa, csq, cnorm, gamma_ss, safety;
-};
 constexpr double kU = 0x1p-24;
 constexpr double kSafety = 1.25;
 
 static double gamma_m(double m) { return m * kU / (1.0 - m * kU); }
 
-Bound bound_constants(const Problem& P, int prec, const std::vector<float>& cabs_host) {
+Bound bound_constants(const Problem& P, int prec) {
     const double ks = (double)P.ks;
     double kappa;
     if (prec == RR_PREC_SPLIT_BF16)
         kappa = (gamma_m(4.0 * ks) + gamma_m(7.0)) * (1.0 + 0x1p-8 + 0x1p-16) + 1.05 * 0x1p-18;
     else
         kappa = gamma_m(16.0 + ks) * (1.0 + 0x1p-23) + 0x1p-24;
-    double c2 = 0.0;
-    for (float c : cabs_host) c2 += (double)c * (double)c;
+    const double c2 = P.cabs_c2;
     const int cb = draw_cb(prec, P.S);
     const int chunks = (int)((P.ncb + cb - 1) / cb);
     const double depth_ss = 16.0 * cb + chunks + 4.0;
@@ -509,14 +393,7 @@ Bound bound_constants(const Problem& P, int prec, const std::vector<float>& cabs
     return b;
 }
 
-static rr_status cabs_host(const Problem& P, std::vector<float>& out, hipStream_t st) {
-    out.assign((size_t)(32 * P.ncb), 0.f);
-    RR_HIP(hipMemcpyAsync(out.data(), P.cabs, out.size() * sizeof(float), hipMemcpyDeviceToHost, st));
-    RR_HIP(hipStreamSynchronize(st));
-    return RR_OK;
-}
-
-static int device_cus(int dev) {
+int device_cus(int dev) {
     static int cached[64] = {};
     if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
     int cus = 0;
@@ -525,7 +402,7 @@ static int device_cus(int dev) {
     return cus;
 }
 
-static ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b) {
+ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b) {
     ContractArgs a{};
     a.op = prec == RR_PREC_SPLIT_BF16 ? P.op_split : P.op_f32;
     a.cabs = P.cabs;
@@ -565,9 +442,9 @@ static hipError_t run_select(WS& w, hipStream_t st) {
 }
 
 // The draw pipeline shared by Monte Carlo and exact enumeration.
-static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begin, uint64_t N, int mode,
-                               double q_or_a, int prec, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
-                               uint64_t capacity, uint64_t* h_count, hipStream_t st) {
+rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begin, uint64_t N, int mode,
+                        double q_or_a, int prec, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
+                        uint64_t capacity, uint64_t* h_count, hipStream_t st, const Tune* tune) {
     auto t_start = std::chrono::steady_clock::now();
     if (N == 0 || !d_keys || !d_M || !h_count || (mode != RR_MODE_QUANTILE && mode != RR_MODE_THRESHOLD) ||
         (prec != RR_PREC_SPLIT_BF16 && prec != RR_PREC_FP32)) {
@@ -608,9 +485,8 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
     rr_status s = ensure_ws(P, cand_cap, acc_cap, band_cap, chunk * wpd, &w);
     if (s != RR_OK) return s;
     if ((s = ensure_streams(P, 4 * nchunks + 5)) != RR_OK) return s;
-    std::vector<float> ch;
-    if ((s = cabs_host(P, ch, st)) != RR_OK) return s;
-    const Bound b = bound_constants(P, prec, ch);
+    const Bound b = bound_constants(P, prec);
+    const Tune tn = tune ? *tune : tune_for(P, prec, exact, N, st);
     const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
     if (exact && !binom) {
         set_error("rr_draw_exact: binomial table allocation failed");
@@ -620,7 +496,7 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
     RR_HIP(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), st));
     {
         Ctl init{};
-        init.k = (uint32_t)k;
+        init.ac.k = (uint32_t)k;
         init.U = INFINITY;
         if (mode == RR_MODE_THRESHOLD) {
             float u = (float)q_or_a;
@@ -657,7 +533,7 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
         g.out = w.bits[bsel];
         RR_HIP(hipEventRecord(ev_t[4 * c + 2], P.gen_stream));
         const uint64_t gen_units = exact ? (num + 63) / 64 : num;
-        RR_HIP(launch_gen(P.S, exact, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * kGenWgPerCu),
+        RR_HIP(launch_gen(P.S, exact, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * tn.gen_wg),
                           P.gen_stream));
         RR_HIP(hipEventRecord(ev_t[4 * c + 3], P.gen_stream));
         RR_HIP(hipEventRecord(ev_ready[bsel], P.gen_stream));
@@ -666,9 +542,9 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
         a.num = num;
         a.key_begin = key_begin + off;
         a.U = (mode == RR_MODE_QUANTILE && c == 0) ? nullptr : &w.ctl->U;
-        const uint64_t tiles = (num + contract_tile(prec, P.S) - 1) / contract_tile(prec, P.S);
+        const uint64_t tiles = (num + contract_tile(prec, P.S, tn.db) - 1) / contract_tile(prec, P.S, tn.db);
         RR_HIP(hipEventRecord(ev_t[4 * c], st));
-        RR_HIP(launch_contract(P.S, prec, a, (int)std::min<uint64_t>(tiles, (uint64_t)cus), st));
+        RR_HIP(launch_contract(P.S, prec, tn.db, false, a, (int)std::min<uint64_t>(tiles, (uint64_t)cus), st));
         RR_HIP(hipEventRecord(ev_t[4 * c + 1], st));
         RR_HIP(hipEventRecord(ev_free[bsel], st));
         if (mode == RR_MODE_QUANTILE && c + 1 < nchunks && (c == 0 || c % 8 == 7)) {
@@ -707,7 +583,7 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
     RecheckArgs ra{};
     ra.X64 = P.X64;
     ra.keys = w.band_key;
-    ra.count = &w.ctl->band_count;
+    ra.count = &w.ctl->ac.band_count;
     ra.seed = seed;
     ra.binom = binom;
     ra.n = (int)P.n;
@@ -721,7 +597,7 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
     RR_HIP(hipGetLastError());
     RR_HIP(hipMemcpyAsync(&hc, w.ctl, offsetof(Ctl, hist), hipMemcpyDeviceToHost, st));
     RR_HIP(hipStreamSynchronize(st));
-    if (hc.sel_fail || hc.guard_fail) {
+    if (hc.sel_fail || hc.ac.guard_fail) {
         set_error("rr_draw: selection failed (guard band inconsistent)");
         return RR_E_DEVICE;
     }
@@ -729,7 +605,7 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
         set_error("rr_draw: guard band larger than the recheck capacity");
         return RR_E_UNSUPPORTED;
     }
-    const uint64_t K = hc.acc_count;
+    const uint64_t K = hc.ac.acc_count;
     if (K > capacity) {
         *h_count = K;
         set_error("rr_draw: capacity below the accepted count");
@@ -740,25 +616,14 @@ static rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t k
         return RR_E_DEVICE;
     }
     if (K > 0) {
-        const uint32_t n = (uint32_t)K;
-        const uint32_t chunks = (n + kSortChunk - 1) / kSortChunk;
-        hipLaunchKernelGGL(sort_chunk_kernel, dim3(chunks), dim3(1024), 0, st, w.acc_key, n, w.sk[0], w.si[0]);
-        int cur = 0;
-        for (uint32_t width = kSortChunk; width < n; width *= 2) {
-            hipLaunchKernelGGL(merge_pass_kernel, dim3((n + 255) / 256), dim3(256), 0, st, w.sk[cur], w.si[cur], n,
-                               width, w.sk[cur ^ 1], w.si[cur ^ 1]);
-            cur ^= 1;
-        }
-        hipLaunchKernelGGL(gather_out_kernel, dim3((n + 255) / 256), dim3(256), 0, st, w.sk[cur], w.si[cur], n,
-                           w.acc_m, w.acc_flag, d_keys, d_M, d_flags);
-        RR_HIP(hipGetLastError());
+        RR_HIP(sort_accepted(w.acc_key, w.acc_m, w.acc_flag, (uint32_t)K, w.sk, w.si, d_keys, d_M, d_flags, st));
         RR_HIP(hipStreamSynchronize(st));
     }
     *h_count = K;
     g_timing.contract_ms = contract_ms;
     g_timing.gen_ms = gen_ms;
     g_timing.launches = launches;
-    g_timing.band = hc.band_count;
+    g_timing.band = hc.ac.band_count;
     g_timing.total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return RR_OK;
@@ -793,6 +658,7 @@ void rr_free(rr_problem* p) {
     hipFree(P.ws);
     for (hipEvent_t e : P.events) hipEventDestroy(e);
     if (P.gen_stream) hipStreamDestroy(P.gen_stream);
+    free_batch_state(P);
     delete p;
 }
 
@@ -813,7 +679,7 @@ rr_status rr_draw_balance(rr_problem* p, uint64_t seed, uint64_t key_begin, uint
         return RR_E_ARG;
     }
     return draw_pipeline(p->P, false, seed, key_begin, num_draws, mode, q_or_a, precision, d_keys, d_M, d_flags,
-                         capacity, h_count, (hipStream_t)stream);
+                         capacity, h_count, (hipStream_t)stream, nullptr);
 }
 
 rr_status rr_draw_exact(rr_problem* p, int mode, double q_or_a, int precision, uint64_t* d_keys, double* d_M,
@@ -828,7 +694,7 @@ rr_status rr_draw_exact(rr_problem* p, int mode, double q_or_a, int precision, u
         return RR_E_RANGE;
     }
     return draw_pipeline(p->P, true, 0, 0, total, mode, q_or_a, precision, d_keys, d_M, d_flags, capacity, h_count,
-                         (hipStream_t)stream);
+                         (hipStream_t)stream, nullptr);
 }
 
 rr_status rr_regenerate(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys, uint64_t K,
@@ -868,10 +734,7 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
     hipStream_t st = (hipStream_t)stream;
     const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
     if (d_M32) {
-        std::vector<float> ch;
-        rr_status s = cabs_host(P, ch, st);
-        if (s != RR_OK) return s;
-        const Bound b = bound_constants(P, precision, ch);
+        const Bound b = bound_constants(P, precision);
         uint32_t* bits = nullptr;
         RR_HIP(hipMalloc(&bits, sizeof(uint32_t) * 8 * P.S * K));
         GenArgs g{};
@@ -891,8 +754,8 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
         a.keylist = d_keys;
         a.out_m32 = d_M32;
         a.out_err = d_err;
-        const uint64_t tiles = (K + contract_tile(precision, P.S) - 1) / contract_tile(precision, P.S);
-        if (e == hipSuccess) e = launch_contract(P.S, precision, a, (int)std::min<uint64_t>(tiles, (uint64_t)cus), st);
+        const uint64_t tiles = (K + contract_tile(precision, P.S, 0) - 1) / contract_tile(precision, P.S, 0);
+        if (e == hipSuccess) e = launch_contract(P.S, precision, 0, false, a, (int)std::min<uint64_t>(tiles, (uint64_t)cus), st);
         hipError_t e2 = hipStreamSynchronize(st);
         hipFree(bits);
         RR_HIP(e);
@@ -921,39 +784,6 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
         RR_HIP(e2);
     }
     RR_HIP(hipStreamSynchronize(st));
-    return RR_OK;
-}
-
-rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob, const uint64_t* seeds, uint64_t key_begin,
-                                  uint64_t num_draws, int mode, double q_or_a, int precision,
-                                  uint64_t* const* d_keys, double* const* d_M, uint64_t capacity,
-                                  uint64_t* h_counts, void* stream) {
-    if (!P || nprob < 0 || (nprob > 0 && (!seeds || !d_keys || !d_M || !h_counts))) {
-        set_error("rr_draw_balance_batched: invalid argument");
-        return RR_E_ARG;
-    }
-    double total = 0, ck = 0, gk = 0;
-    int64_t launches = 0;
-    uint64_t band = 0;
-    for (int64_t i = 0; i < nprob; ++i) {
-        if (!P[i]) {
-            set_error("rr_draw_balance_batched: null handle");
-            return RR_E_ARG;
-        }
-        rr_status s = draw_pipeline(P[i]->P, false, seeds[i], key_begin, num_draws, mode, q_or_a, precision,
-                                    d_keys[i], d_M[i], nullptr, capacity, &h_counts[i], (hipStream_t)stream);
-        if (s != RR_OK) return s;
-        total += g_timing.total_ms;
-        ck += g_timing.contract_ms;
-        gk += g_timing.gen_ms;
-        launches += g_timing.launches;
-        band += g_timing.band;
-    }
-    g_timing.total_ms = total;
-    g_timing.contract_ms = ck;
-    g_timing.gen_ms = gk;
-    g_timing.launches = launches;
-    g_timing.band = band;
     return RR_OK;
 }
 

@@ -1,0 +1,199 @@
+"""Batched pools (one graph launch over many problems) vs single-pool calls and the oracle.
+
+Bar: for every pool the accepted keys equal those of rr_draw_balance on the same problem,
+bit for bit, and so do the reported M values (the same kernels compute them); for pools the
+oracle can afford, the keys equal the oracle's.  At the full 512-problem size, sampled pools
+are compared with single-pool calls, and sampled draws with the oracle's FP64 M (accepted
+M <= rejected M, accepted M within 1e-4 relative).
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import pipeline  # noqa: E402
+from paper_2501_07642_amd import inputs  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_07642_amd as rr
+    rr.load()
+    return rr
+
+
+DEV = "cuda:0"
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def u64(t):
+    return t.cpu().numpy().astype(np.uint64)
+
+
+# one shape per bitmask class (S = 1, 2, 4, 8), ragged n and d, two pools sharing a shape
+SHAPES = [(50, 10), (61, 3), (200, 40), (300, 33), (257, 100), (700, 64), (1000, 250), (1024, 500),
+          (1500, 130), (2000, 500), (2000, 500), (99, 98)]
+
+
+def _problems(rr, shapes, seed0=900, dtype=np.float32):
+    Xs, Ps, seeds = [], [], []
+    for i, (n, d) in enumerate(shapes):
+        X = inputs.gaussian_X(n, d, seed0 + i, dtype=dtype)
+        Xs.append(X)
+        Ps.append(rr.rr_prepare(dev(X), n // 2, 1e-2))
+        seeds.append(0xBA7C4000 + i)
+    return Xs, Ps, seeds
+
+
+def _single(rr, P, seed, N, mode, qa, prec):
+    keys, M, _ = rr.rr_draw_balance(P, seed, 0, N, mode, qa, prec)
+    return u64(keys), M.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["split", "fp32"])
+def test_batched_equals_single_quantile(rr, prec):
+    pr = rr.PREC_SPLIT_BF16 if prec == "split" else rr.PREC_FP32
+    N, q = 20_000, 0.01
+    say(f"batched vs single, quantile, {prec}")
+    Xs, Ps, seeds = _problems(rr, SHAPES)
+    out = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_QUANTILE, q, pr)
+    t = rr.rr_last_timing()
+    say(f"  graph {t['contract_ms']:.2f} ms, {t['launches']} kernels, band {t['band']}")
+    for i, (keys, M) in enumerate(out):
+        want_k, want_M = _single(rr, Ps[i], seeds[i], N, rr.MODE_QUANTILE, q, pr)
+        assert len(want_k) == 200
+        np.testing.assert_array_equal(u64(keys), want_k)
+        np.testing.assert_array_equal(M.cpu().numpy(), want_M)
+    # the oracle on the small pools
+    for i in (0, 1, 2):
+        n, d = SHAPES[i]
+        acc, _, _ = pipeline.draw_balance(Xs[i].astype(np.float64), n // 2, 1e-2, seeds[i], 0, N, "quantile", q)
+        np.testing.assert_array_equal(u64(out[i][0]), acc)
+
+
+def test_batched_threshold_and_ragged(rr):
+    say("batched vs single, threshold, ragged draw count")
+    shapes = [(50, 10), (300, 33), (1000, 250), (2000, 20)]
+    Xs, Ps, seeds = _problems(rr, shapes, seed0=950)
+    N = 4_099
+    for a in (0.0, 8.0, 60.0):
+        out = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_THRESHOLD, a, rr.PREC_SPLIT_BF16, capacity=N)
+        for i, (keys, M) in enumerate(out):
+            want_k, want_M = _single(rr, Ps[i], seeds[i], N, rr.MODE_THRESHOLD, a, rr.PREC_SPLIT_BF16)
+            np.testing.assert_array_equal(u64(keys), want_k)
+            np.testing.assert_array_equal(M.cpu().numpy(), want_M)
+    acc, _, _ = pipeline.draw_balance(Xs[0].astype(np.float64), 25, 1e-2, seeds[0], 0, N, "threshold", 8.0)
+    out = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_THRESHOLD, 8.0, rr.PREC_SPLIT_BF16, capacity=N)
+    np.testing.assert_array_equal(u64(out[0][0]), acc)
+
+
+def test_batched_replay_and_many_accepted(rr):
+    say("batched graph replay, new arguments, > 2048 accepted per pool")
+    shapes = [(120, 12), (640, 64)]
+    _, Ps, seeds = _problems(rr, shapes, seed0=970)
+    N = 30_000
+    first = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_QUANTILE, 0.2, rr.PREC_SPLIT_BF16)
+    again = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_QUANTILE, 0.2, rr.PREC_SPLIT_BF16)
+    for (k1, m1), (k2, m2) in zip(first, again):
+        assert len(k1) == 6000
+        np.testing.assert_array_equal(u64(k1), u64(k2))
+        np.testing.assert_array_equal(m1.cpu().numpy(), m2.cpu().numpy())
+    seeds2 = [s + 17 for s in seeds]
+    out = rr.rr_draw_balance_batched(Ps, seeds2, 5, N, rr.MODE_QUANTILE, 0.2, rr.PREC_SPLIT_BF16)
+    for i, (keys, M) in enumerate(out):
+        kk, MM, _ = rr.rr_draw_balance(Ps[i], seeds2[i], 5, N, rr.MODE_QUANTILE, 0.2, rr.PREC_SPLIT_BF16)
+        np.testing.assert_array_equal(u64(keys), u64(kk))
+        np.testing.assert_array_equal(M.cpu().numpy(), MM.cpu().numpy())
+
+
+def test_batched_errors(rr):
+    say("batched error paths")
+    _, Ps, seeds = _problems(rr, [(60, 5), (80, 6)], seed0=990)
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_draw_balance_batched(Ps, seeds, 0, 1000, rr.MODE_QUANTILE, 0.1, rr.PREC_SPLIT_BF16, capacity=50)
+    assert e.value.status == "RR_E_CAPACITY"
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_draw_balance_batched(Ps, seeds, 0, 1000, rr.MODE_QUANTILE, 1.5, rr.PREC_SPLIT_BF16)
+    assert e.value.status == "RR_E_ARG"
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_draw_balance_batched(Ps, seeds, 0, 1000, rr.MODE_THRESHOLD, 1e9, rr.PREC_SPLIT_BF16, capacity=10)
+    assert e.value.status == "RR_E_CAPACITY"
+    assert rr.rr_draw_balance_batched([], [], 0, 1000) == []
+
+
+def test_batched_512_sampled(rr):
+    """The full batched workload: 512 pools, n ~ U[50, 2000], d ~ U[10, 500], 1e5 draws each."""
+    w = inputs.WORKLOADS["batched_512"]
+    say("batched 512 pools: prepare")
+    Ps, seeds, Xs = [], [], {}
+    rng = np.random.default_rng(12)
+    sample = sorted(rng.choice(w["num_problems"], size=12, replace=False).tolist())
+    for p in range(w["num_problems"]):
+        X, n1, seed = inputs.batched_problem(p)
+        if p in sample[:3]:
+            Xs[p] = X
+        Ps.append(rr.rr_prepare(dev(X), n1, w["ridge_rel"]))
+        seeds.append(seed)
+    say("batched 512 pools: run")
+    N, q = w["num_draws"], w["q"]
+    out = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_QUANTILE, q, rr.PREC_SPLIT_BF16)
+    t = rr.rr_last_timing()
+    say(f"  graph {t['contract_ms']:.1f} ms, {t['launches']} kernels, band {t['band']}")
+    for keys, _ in out:
+        k = u64(keys)
+        assert len(k) == 1000 and np.all(np.diff(k.astype(np.float64)) > 0) and k[-1] < N
+    for p in sample:
+        want_k, want_M = _single(rr, Ps[p], seeds[p], N, rr.MODE_QUANTILE, q, rr.PREC_SPLIT_BF16)
+        np.testing.assert_array_equal(u64(out[p][0]), want_k)
+        np.testing.assert_array_equal(out[p][1].cpu().numpy(), want_M)
+    for p in sample[:3]:
+        X = Xs[p].astype(np.float64)
+        n1 = X.shape[0] // 2
+        acc = u64(out[p][0])
+        Macc = pipeline.balance_of_keys(X, n1, w["ridge_rel"], seeds[p], acc)
+        rest = np.setdiff1d(np.arange(N, dtype=np.uint64), acc)
+        rej = rng.choice(rest, size=1500, replace=False)
+        Mrej = pipeline.balance_of_keys(X, n1, w["ridge_rel"], seeds[p], rej)
+        say(f"  pool {p}: n={X.shape[0]} d={X.shape[1]} max acc {Macc.max():.6f} min rej {Mrej.min():.6f}")
+        assert Macc.max() <= Mrej.min() * (1 + 1e-10)
+        np.testing.assert_allclose(out[p][1].cpu().numpy(), Macc, rtol=1e-4)
+
+
+def test_autotuner_file(rr, tmp_path):
+    """A call large enough to tune writes its bucket's choice to RR_TUNE_FILE."""
+    path = tmp_path / "tune.json"
+    os.environ["RR_TUNE_FILE"] = str(path)
+    try:
+        say("autotuner: fp32, n=90, d=7, 2^20 draws")
+        X = inputs.gaussian_X(90, 7, 5)
+        P = rr.rr_prepare(dev(X), 45, 0.0)
+        N = 1 << 20
+        keys, _, _ = rr.rr_draw_balance(P, 3, 0, N, rr.MODE_QUANTILE, 1e-4, rr.PREC_FP32)
+        doc = json.loads(path.read_text())
+        ent = [e for e in doc["rr_tune"] if e["prec"] == rr.PREC_FP32 and e["S"] == 1]
+        assert ent and ent[0]["db"] in (1, 2) and ent[0]["gen_wg"] in (2, 3, 4)
+        say(f"  chose {ent[0]}")
+        # the tuned configuration gives the same pool as the oracle
+        acc, _, _ = pipeline.draw_balance(X, 45, 0.0, 3, 0, 200_000, "quantile", 1e-3)
+        k2, _, _ = rr.rr_draw_balance(P, 3, 0, 200_000, rr.MODE_QUANTILE, 1e-3, rr.PREC_FP32)
+        np.testing.assert_array_equal(u64(k2), acc)
+        assert len(u64(keys)) == 105
+    finally:
+        os.environ.pop("RR_TUNE_FILE", None)
