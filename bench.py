@@ -26,6 +26,32 @@ PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 (matrix / vector)
 
 
+CONTRACT_SRC = os.path.join(ROOT, "paper_2501_07642_amd", "csrc", "rr_contract.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_traffic_stream_n1000_d1000.md")
+
+
+def measured_traffic():
+    """HBM bytes per contraction launch from the committed PMC summary, or None when the
+    summary is missing or was taken on a different contraction source."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    src = hashlib.sha256(open(CONTRACT_SRC, "rb").read()).hexdigest()
+    if fields.get("contract_source_sha256") != src:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(X, w, sample):
     """The oracle, as it stands, on the first `sample` draws of the workload."""
     import numpy as np
@@ -45,6 +71,60 @@ def cpu_baseline(X, w, sample):
                       f"FP64 textbook M, q-quantile acceptance over the sample ({dt:.1f} s)"}
 
 
+def run_batched(args, rr, inputs, np, torch):
+    """Batched pools: one graph launch over all pools vs one rr_draw_balance call per pool."""
+    w = inputs.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    N, q = w["num_draws"], w["q"]
+    if args.draws:
+        N = args.draws
+    t0 = time.perf_counter()
+    Ps, seeds = [], []
+    for p in range(w["num_problems"]):
+        X, n1, seed = inputs.batched_problem(p, args.workload)
+        Ps.append(rr.rr_prepare(torch.from_numpy(X).to(dev), n1, w["ridge_rel"]))
+        seeds.append(seed)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    shapes = inputs.batched_shapes(w["num_problems"], w["shape_seed"])
+    flops = sum(4.0 * n * d for n, _, d in shapes) * N
+    for _ in range(args.warmup):
+        rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_QUANTILE, q, rr.PREC_SPLIT_BF16)
+    torch.cuda.synchronize()
+    graph_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_QUANTILE, q, rr.PREC_SPLIT_BF16)
+        graph_ms += rr.rr_last_timing()["contract_ms"]
+    torch.cuda.synchronize()
+    ms_per_step = 1000.0 * (time.perf_counter() - t0) / args.steps
+    kernels = rr.rr_last_timing()["launches"]
+    # per-pool launch sequences, one pass
+    t1 = time.perf_counter()
+    same = True
+    for i, P in enumerate(Ps):
+        keys, M, _ = rr.rr_draw_balance(P, seeds[i], 0, N, rr.MODE_QUANTILE, q, rr.PREC_SPLIT_BF16)
+        if i % 64 == 0:
+            same = same and bool(torch.equal(keys, out[i][0])) and bool(torch.equal(M, out[i][1]))
+    torch.cuda.synchronize()
+    loop_ms = 1000.0 * (time.perf_counter() - t1)
+    total = w["num_problems"] * N
+    value = total / (ms_per_step / 1000.0)
+    achieved = flops / (graph_ms / args.steps / 1000.0) / 1e12
+    print(json.dumps({
+        "metric": "batched pools: balance-checked draws/s (512 pools, n~U[50,2000], d~U[10,500])",
+        "value": value, "unit": "draws/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": args.workload, "num_problems": w["num_problems"], "num_draws": N, "q": q,
+                   "step": "rr_draw_balance_batched (one graph launch)"},
+        "graph_gpu_ms_per_step": graph_ms / args.steps, "graph_kernels": kernels,
+        "mfma_tflops_over_graph": achieved, "frac_bf16_peak_over_graph": achieved / PEAK_BF16_TFLOPS,
+        "per_pool_calls": {"ms": loop_ms, "draws_per_s": total / (loop_ms / 1000.0),
+                           "batched_speedup": loop_ms / ms_per_step, "same_results_sampled": same},
+        "prepare_s_all_pools": prep_s}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +135,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (PMC byte-counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this hot path runs on one GPU; --gpus {args.gpus} is not supported "
@@ -67,7 +149,15 @@ def main():
     import paper_2501_07642_amd as rr
     from paper_2501_07642_amd import inputs
 
+    if args.calibrate_copy_mb:
+        src = torch.ones(args.calibrate_copy_mb << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = dict(inputs.WORKLOADS[args.workload])
+    if w["kind"] == "batched":
+        return run_batched(args, rr, inputs, np, torch)
     if args.draws:
         w["num_draws"] = args.draws
     n, n1, d, N, q = w["n"], w["n1"], w["d"], w["num_draws"], w["q"]
@@ -117,7 +207,7 @@ def main():
     avg_launch_ms = contract_ms / max(launches, 1)
     achieved = flops_per_draw * N * args.steps / (contract_ms / 1000.0) / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_BF16_TFLOPS, "traffic": measured_traffic(),
                 "kernel": "contract_kernel<split BF16> (W X~ on 32x32x16 BF16 MFMA + reduce + prefilter)",
                 "avg_launch_ms": avg_launch_ms, "launches_per_step": launches / args.steps,
                 "algorithmic_flops_per_draw": flops_per_draw,

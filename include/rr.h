@@ -184,6 +184,34 @@ rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob, const uin
                                   double* const* d_M, uint64_t capacity, uint64_t* h_counts,
                                   void* stream);
 
+/*
+ * Design diagnostics (host computation, no device work): closed forms for choosing the
+ * acceptance probability q (section 2.2; Appendix A parts A-D), for n1 treated and n0
+ * control units, d whitened covariates, outcome noise sd sigma and R^2 of the outcome on
+ * the covariates (0 <= r2 < 1).  M is taken as chi^2_d under complete randomization.
+ */
+typedef struct {
+    double c_q;            /* q-quantile of chi^2_d: acceptance threshold on the scale of M */
+    double a_q;            /* the same threshold on the paper's scale, (1/n1 + 1/n0) c_q */
+    double v_a;            /* Pr(chi^2_{d+2} <= c_q) / Pr(chi^2_d <= c_q): variance shrinkage of
+                              each whitened covariate mean difference (Appendix A part C) */
+    double expected_M;     /* E[M | accepted] = d v_a */
+    double rmse_reduction; /* 1 - sqrt((1 + v_a s) / (1 + s)), s = r2 / (1 - r2) */
+    double mse_complete;   /* (1/n1 + 1/n0)(sigma^2 + s sigma^2): complete randomization */
+    double mse_accept;     /* (1/n1 + 1/n0)(sigma^2 + v_a s sigma^2): conditional on acceptance */
+} rr_design;
+
+/* Closed forms at acceptance probability q in (0, 1] (q = 1: c_q = inf, v_a = 1).
+ * Errors: RR_E_ARG (n1, n0, d < 1, sigma <= 0, r2 outside [0, 1), q outside (0, 1]). */
+rr_status rr_diagnose(int64_t n1, int64_t n0, int64_t d, double q, double sigma, double r2,
+                      rr_design* out);
+
+/* q* (Appendix A part D): the largest q with mse_accept(q) <= tau^2 / (z_{1-alpha/2} +
+ * z_power)^2, searched over [q_lo, 1] (mse_accept increases with q).  *q_star = 1 when q = 1
+ * already meets the target.  Errors: RR_E_ARG; RR_E_RANGE when no q >= q_lo meets it. */
+rr_status rr_q_star(int64_t n1, int64_t n0, int64_t d, double sigma, double r2, double tau,
+                    double alpha, double power, double q_lo, double* q_star);
+
 /* Timing of the last rr_draw_balance / rr_draw_exact / rr_draw_balance_batched call on
  * this thread: host wall milliseconds of the call, and HIP-event milliseconds summed over the
  * launches of the contraction kernel (on the caller's stream) and of the generation kernel

@@ -29,7 +29,14 @@ SIGNATURES = [
     ("rr_rand_test", _I, [_P, _U64, _I, _P, _U64, _U64, _P, _P, _I64, _P, C.POINTER(_D), _P]),
     ("rr_draw_balance_batched", _I, [_P, _I64, _P, _U64, _U64, _I, _D, _I, _P, _P, _U64, _P, _P]),
     ("rr_last_timing", _I, [C.POINTER(_D), C.POINTER(_D), C.POINTER(_D), C.POINTER(_I64), C.POINTER(_U64)]),
+    ("rr_diagnose", _I, [_I64, _I64, _I64, _D, _D, _D, _P]),
+    ("rr_q_star", _I, [_I64, _I64, _I64, _D, _D, _D, _D, _D, _D, C.POINTER(_D)]),
 ]
+
+
+class _Design(C.Structure):
+    _fields_ = [(name, C.c_double) for name in ("c_q", "a_q", "v_a", "expected_M", "rmse_reduction",
+                                                "mse_complete", "mse_accept")]
 
 _lib = None
 
@@ -234,3 +241,21 @@ def rr_last_timing():
     t, ck, gk, nl, band = C.c_double(), C.c_double(), C.c_double(), C.c_int64(), C.c_uint64()
     _check(load().rr_last_timing(C.byref(t), C.byref(ck), C.byref(gk), C.byref(nl), C.byref(band)))
     return dict(total_ms=t.value, contract_ms=ck.value, gen_ms=gk.value, launches=nl.value, band=band.value)
+
+
+def rr_diagnose(n1, n0, d, q, sigma=1.0, r2=0.0):
+    """Design closed forms at acceptance probability q (host computation in the library)."""
+    out = _Design()
+    _check(load().rr_diagnose(n1, n0, d, float(q), float(sigma), float(r2), C.cast(C.byref(out), C.c_void_p)))
+    return {name: getattr(out, name) for name, _ in _Design._fields_}
+
+
+def rr_q_star(n1, n0, d, sigma, r2, tau, alpha=0.05, power=0.8, q_lo=1e-300):
+    """Largest q meeting the power-derived RMSE target, or None when no q >= q_lo does."""
+    q = C.c_double()
+    st = load().rr_q_star(n1, n0, d, float(sigma), float(r2), float(tau), float(alpha), float(power),
+                          float(q_lo), C.byref(q))
+    if STATUS.get(st) == "RR_E_RANGE":
+        return None
+    _check(st)
+    return q.value

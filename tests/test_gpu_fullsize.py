@@ -1,0 +1,104 @@
+"""Full-size pools at n = d = 1000 (the launch configuration the benchmark times), checked
+on samples the oracle computes one by one and on properties that hold at any size.
+
+  precision_n1000_d1000: 2e5 draws, AR(1) + Student-t covariates, q = 0.01 (2000 kept),
+      both operand forms: identical accepted sets; oracle M of every accepted draw and of
+      3000 sampled rejected draws: accepted max <= rejected min; M within 1e-9 (rechecked)
+      or 1e-4 (FP32) relative; randomization-test counts equal the oracle's exactly.
+  stream_n1000_d1000: 1e8 draws, q = 1.2e-5 (1200 kept), streaming prefilter: the same
+      sampled checks, and the FP32 form accepts the same set.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import pipeline  # noqa: E402
+from paper_2501_07642_amd import inputs  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2501_07642_amd as rr
+    rr.load()
+    return rr
+
+
+DEV = "cuda:0"
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def u64(t):
+    return t.cpu().numpy().astype(np.uint64)
+
+
+def _sampled_checks(X, w, keys, M, flags, rng, n_rej=3000):
+    acc = u64(keys)
+    N = w["num_draws"]
+    assert len(acc) == int(np.ceil(w["q"] * N * (1 - 1e-12)))
+    assert np.all(np.diff(acc.astype(np.float64)) > 0) and acc[-1] < N
+    Macc = pipeline.balance_of_keys(X, w["n1"], w["ridge_rel"], w["seed"], acc)
+    rej = rng.integers(0, N, size=n_rej + 200, dtype=np.uint64)
+    rej = np.setdiff1d(rej, acc)[:n_rej]
+    Mrej = pipeline.balance_of_keys(X, w["n1"], w["ridge_rel"], w["seed"], rej)
+    say(f"  max accepted M {Macc.max():.9f}, min sampled rejected M {Mrej.min():.9f}")
+    assert Macc.max() <= Mrej.min() * (1 + 1e-10)
+    Mg, fl = M.cpu().numpy(), flags.cpu().numpy().astype(bool)
+    if fl.any():
+        np.testing.assert_allclose(Mg[fl], Macc[fl], rtol=1e-9)
+    np.testing.assert_allclose(Mg[~fl], Macc[~fl], rtol=1e-4)
+    rel = np.abs(Mg[~fl] - Macc[~fl]) / Macc[~fl]
+    say(f"  FP32 values: max rel err {rel.max() if len(rel) else 0:.3e}; rechecked {int(fl.sum())}")
+    return acc
+
+
+def test_precision_pool_both_forms_and_frt(rr):
+    name = "precision_n1000_d1000"
+    w = inputs.WORKLOADS[name]
+    say("precision pool n=d=1000, 2e5 draws")
+    X = inputs.workload_X(name)
+    P = rr.rr_prepare(dev(X), w["n1"], w["ridge_rel"])
+    ks, Ms, fs = rr.rr_draw_balance(P, w["seed"], 0, w["num_draws"], rr.MODE_QUANTILE, w["q"], rr.PREC_SPLIT_BF16)
+    k32, M32, f32 = rr.rr_draw_balance(P, w["seed"], 0, w["num_draws"], rr.MODE_QUANTILE, w["q"], rr.PREC_FP32)
+    np.testing.assert_array_equal(u64(ks), u64(k32))
+    acc = _sampled_checks(X, w, ks, Ms, fs, np.random.default_rng(31))
+    _sampled_checks(X, w, k32, M32, f32, np.random.default_rng(32), n_rej=500)
+    # randomization test on the accepted pool
+    obs = inputs.obs_pick(len(acc), w["obs_seed"])
+    wo = pipeline.regenerate(w["seed"], acc[obs:obs + 1], w["n"], w["n1"])[0]
+    Y = inputs.outcomes(X, wo, w["tau"], w["noise_sd"], w["y_seed"])
+    taus = w["taus"][::10]
+    counts, tau_hat = rr.rr_rand_test(P, w["seed"], ks, obs, dev(Y), taus)
+    ref = pipeline.rand_test_keys(w["seed"], acc, w["n"], w["n1"], obs, Y, taus)
+    assert counts.cpu().tolist() == ref["counts"]
+    assert abs(tau_hat - ref["tau_hat"]) <= 1e-12 * max(1.0, abs(ref["tau_hat"]))
+
+
+def test_stream_pool_sampled(rr):
+    name = "stream_n1000_d1000"
+    w = inputs.WORKLOADS[name]
+    say("stream pool n=d=1000, 1e8 draws, q=1.2e-5")
+    X = inputs.workload_X(name)
+    P = rr.rr_prepare(dev(X), w["n1"], w["ridge_rel"])
+    ks, Ms, fs = rr.rr_draw_balance(P, w["seed"], 0, w["num_draws"], rr.MODE_QUANTILE, w["q"], rr.PREC_SPLIT_BF16)
+    t = rr.rr_last_timing()
+    say(f"  split: {t['total_ms']:.1f} ms, band {t['band']}")
+    _sampled_checks(X, w, ks, Ms, fs, np.random.default_rng(41))
+    k32, _, _ = rr.rr_draw_balance(P, w["seed"], 0, w["num_draws"], rr.MODE_QUANTILE, w["q"], rr.PREC_FP32)
+    say(f"  fp32: {rr.rr_last_timing()['total_ms']:.1f} ms")
+    np.testing.assert_array_equal(u64(ks), u64(k32))
