@@ -52,6 +52,7 @@ typedef enum {
 enum { RR_MODE_QUANTILE = 0, RR_MODE_THRESHOLD = 1 };
 enum { RR_PREC_SPLIT_BF16 = 0, RR_PREC_FP32 = 1 };
 enum { RR_X_FP64 = 0, RR_X_FP32 = 1 };
+enum { RR_METRIC_MAHALANOBIS = 0, RR_METRIC_DIAGONAL = 1 };
 
 /* Largest unit count of a Monte Carlo problem in this build. */
 #define RR_MAX_N 4096
@@ -77,6 +78,20 @@ enum { RR_X_FP64 = 0, RR_X_FP32 = 1 };
  */
 rr_status rr_prepare(const void* d_X, int x_dtype, int64_t n, int64_t d, int64_t ldx,
                      int64_t n1, double ridge_rel, void* stream, rr_problem** out);
+
+/*
+ * rr_prepare_metric -- rr_prepare with a choice of balance metric.
+ *   metric = RR_METRIC_MAHALANOBIS: as rr_prepare (whitening by the Cholesky factor).
+ *   metric = RR_METRIC_DIAGONAL: the covariates are standardised but not decorrelated:
+ *            S_lam is replaced by its diagonal, so M = (n1 n0 / n) sum_j Delta_j^2 /
+ *            (S_jj + lambda), the sum of squared standardised mean differences (section 2.2
+ *            states M for standardised covariates).  Every later call is unchanged.
+ * Errors as rr_prepare (RR_E_SINGULAR: some S_jj + lambda <= 1e-10 max S_jj); RR_E_ARG for an
+ * unknown metric.
+ */
+rr_status rr_prepare_metric(const void* d_X, int x_dtype, int64_t n, int64_t d, int64_t ldx,
+                            int64_t n1, double ridge_rel, int metric, void* stream,
+                            rr_problem** out);
 
 /* Releases a handle and its device memory.  Null is ignored. */
 void rr_free(rr_problem* p);

@@ -17,9 +17,9 @@ import numpy as np
 from . import accept, assign, balance, frt, prep
 
 
-def balance_of_keys(X, n1, ridge_rel, seed, keys, exact=False, batch=10000):
+def balance_of_keys(X, n1, ridge_rel, seed, keys, exact=False, batch=10000, metric="mahalanobis"):
     """M (FP64, textbook form) of the draws with the given keys."""
-    P = prep.prepare(X, n1, ridge_rel)
+    P = prep.prepare(X, n1, ridge_rel, metric)
     n = P["n"]
     keys = np.asarray(keys, dtype=np.uint64)
     out = np.empty(len(keys), dtype=np.float64)
@@ -34,10 +34,10 @@ def balance_of_keys(X, n1, ridge_rel, seed, keys, exact=False, batch=10000):
 
 
 def draw_balance(X, n1, ridge_rel, seed, key_begin, num_draws, mode, q_or_a,
-                 batch=10000):
+                 batch=10000, metric="mahalanobis"):
     """Monte Carlo pool: returns (accepted keys ascending, their M, M of every draw)."""
     keys = np.arange(key_begin, key_begin + num_draws, dtype=np.uint64)
-    M = balance_of_keys(X, n1, ridge_rel, seed, keys, batch=batch)
+    M = balance_of_keys(X, n1, ridge_rel, seed, keys, batch=batch, metric=metric)
     return _accept(keys, M, mode, q_or_a) + (M,)
 
 

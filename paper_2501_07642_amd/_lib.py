@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 MODE_QUANTILE, MODE_THRESHOLD = 0, 1
 PREC_SPLIT_BF16, PREC_FP32 = 0, 1
 X_FP64, X_FP32 = 0, 1
+METRIC_MAHALANOBIS, METRIC_DIAGONAL = 0, 1
 STATUS = {0: "RR_OK", 1: "RR_E_ARG", 2: "RR_E_SINGULAR", 3: "RR_E_CAPACITY", 4: "RR_E_RANGE",
           5: "RR_E_OBS", 6: "RR_E_DEVICE", 7: "RR_E_UNSUPPORTED"}
 
@@ -16,6 +17,7 @@ STATUS = {0: "RR_OK", 1: "RR_E_ARG", 2: "RR_E_SINGULAR", 3: "RR_E_CAPACITY", 4: 
 _P, _I, _I64, _U64, _D = C.c_void_p, C.c_int, C.c_int64, C.c_uint64, C.c_double
 SIGNATURES = [
     ("rr_prepare", _I, [_P, _I, _I64, _I64, _I64, _I64, _D, _P, C.POINTER(_P)]),
+    ("rr_prepare_metric", _I, [_P, _I, _I64, _I64, _I64, _I64, _D, _I, _P, C.POINTER(_P)]),
     ("rr_free", None, [_P]),
     ("rr_last_error", C.c_char_p, []),
     ("rr_problem_n", _I64, [_P]),
@@ -130,7 +132,8 @@ class Problem:
             pass
 
 
-def rr_prepare(X, n1, ridge_rel=0.0):
+def rr_prepare(X, n1, ridge_rel=0.0, metric=None):
+    """Prepare a problem; metric None / METRIC_MAHALANOBIS whitens, METRIC_DIAGONAL standardises."""
     torch = _torch()
     if not X.is_cuda:
         raise ValueError("X must be a device tensor")
@@ -138,7 +141,11 @@ def rr_prepare(X, n1, ridge_rel=0.0):
     dt = {torch.float64: X_FP64, torch.float32: X_FP32}[X.dtype]
     n, d = X.shape
     h = C.c_void_p()
-    _check(load().rr_prepare(_ptr(X), dt, n, d, d, n1, float(ridge_rel), _stream(), C.byref(h)))
+    if metric is None:
+        _check(load().rr_prepare(_ptr(X), dt, n, d, d, n1, float(ridge_rel), _stream(), C.byref(h)))
+    else:
+        _check(load().rr_prepare_metric(_ptr(X), dt, n, d, d, n1, float(ridge_rel), int(metric), _stream(),
+                                        C.byref(h)))
     return Problem(h, X.device)
 
 

@@ -40,6 +40,7 @@ struct Problem {
     int device = 0;
     int64_t n = 0, d = 0, n1 = 0, n0 = 0;
     double ridge_rel = 0, lambda = 0;
+    int metric = RR_METRIC_MAHALANOBIS;
     int S = 0;             // 256-unit chunks per draw: ceil(n / 256)
     int wstride = 0;       // uint32 words per draw bitmask in the internal layout: 8 * S
     int64_t ks = 0;        // K steps of 16 units, a multiple of kKStepsPerStage (units >= n are zero)

@@ -132,6 +132,16 @@ __global__ void potrf_diag_kernel(double* A, int64_t d, int64_t k0, int nb, doub
     }
 }
 
+// Diagonal metric: the factor is diag(sqrt(S_jj + lambda)) (standardise, do not decorrelate).
+__global__ void diag_factor_kernel(double* A, int64_t d, double* pivots, int* bad) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < d; j += (int64_t)gridDim.x * blockDim.x) {
+        const double v = A[j * d + j];
+        pivots[j] = v;
+        if (!(v > 0.0)) *bad = 1;
+        for (int64_t c = 0; c < d; ++c) A[j * d + c] = c == j ? (v > 0.0 ? sqrt(v) : 1.0) : 0.0;
+    }
+}
+
 // Rows r0..r0+rows-1 of the nb-column block at column k0 of Mtx (leading dim ldm) are
 // replaced by x with x L11^T = row, L11 the nb x nb lower block of L at (k0, k0).
 __global__ void trsm_rows_kernel(double* Mtx, int64_t ldm, int64_t r0, int64_t rows, int64_t col0,
@@ -224,9 +234,10 @@ static hipError_t gemm_nt(hipStream_t st, int64_t M, int64_t N, int64_t K, doubl
 int pow2_chunks(int n);
 
 rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_t ldx, int64_t n1,
-                       double ridge_rel, hipStream_t st, rr_problem** out) {
+                       double ridge_rel, int metric, hipStream_t st, rr_problem** out) {
     if (!dX || !out || n < 2 || d < 1 || ldx < d || n1 < 1 || n1 > n - 1 || !(ridge_rel >= 0.0) ||
-        (x_dtype != RR_X_FP64 && x_dtype != RR_X_FP32)) {
+        (x_dtype != RR_X_FP64 && x_dtype != RR_X_FP32) ||
+        (metric != RR_METRIC_MAHALANOBIS && metric != RR_METRIC_DIAGONAL)) {
         set_error("rr_prepare: invalid argument");
         return RR_E_ARG;
     }
@@ -242,6 +253,7 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     P.n1 = n1;
     P.n0 = n - n1;
     P.ridge_rel = ridge_rel;
+    P.metric = metric;
     P.S = pow2_chunks((int)n);
     P.wstride = 8 * P.S;
     P.ks = kKStepsPerStage * ((n + kKStepsPerStage * kKStep - 1) / (kKStepsPerStage * kKStep));  // whole LDS stages
@@ -287,7 +299,11 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     RR_PHIP(gemm_nt(st, d, d, n, 1.0 / (double)(n - 1), P.X64, 1, d, P.X64, 1, d, 0.0, A, d));
     hipLaunchKernelGGL(ridge_kernel, dim3(1), dim3(256), 0, st, A, d, ridge_rel, scal);
     RR_PHIP(hipGetLastError());
-    for (int64_t k0 = 0; k0 < d; k0 += kNB) {
+    if (metric == RR_METRIC_DIAGONAL) {
+        hipLaunchKernelGGL(diag_factor_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, A, d, piv, bad);
+        RR_PHIP(hipGetLastError());
+    }
+    for (int64_t k0 = 0; k0 < d && metric == RR_METRIC_MAHALANOBIS; k0 += kNB) {
         const int nb = (int)std::min<int64_t>(kNB, d - k0);
         hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(kNB), 0, st, A, d, k0, nb, piv, bad);
         RR_PHIP(hipGetLastError());

@@ -631,7 +631,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
 
 int pow2_chunks(int n);
 rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_t ldx, int64_t n1,
-                       double ridge_rel, hipStream_t st, rr_problem** out);
+                       double ridge_rel, int metric, hipStream_t st, rr_problem** out);
 
 }  // namespace rr
 
@@ -643,7 +643,12 @@ const char* rr_last_error(void) { return g_err.c_str(); }
 
 rr_status rr_prepare(const void* d_X, int x_dtype, int64_t n, int64_t d, int64_t ldx, int64_t n1,
                      double ridge_rel, void* stream, rr_problem** out) {
-    return prepare_impl(d_X, x_dtype, n, d, ldx, n1, ridge_rel, (hipStream_t)stream, out);
+    return prepare_impl(d_X, x_dtype, n, d, ldx, n1, ridge_rel, RR_METRIC_MAHALANOBIS, (hipStream_t)stream, out);
+}
+
+rr_status rr_prepare_metric(const void* d_X, int x_dtype, int64_t n, int64_t d, int64_t ldx, int64_t n1,
+                            double ridge_rel, int metric, void* stream, rr_problem** out) {
+    return prepare_impl(d_X, x_dtype, n, d, ldx, n1, ridge_rel, metric, (hipStream_t)stream, out);
 }
 
 void rr_free(rr_problem* p) {

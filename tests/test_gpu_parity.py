@@ -195,3 +195,27 @@ def test_errors(rr):
     with pytest.raises(rr.RRError) as e:
         rr.rr_draw_balance(P, 1, 0, 1000, rr.MODE_QUANTILE, 0.0, rr.PREC_SPLIT_BF16)
     assert e.value.status == "RR_E_ARG"
+
+
+@pytest.mark.parametrize("prec", ["split", "fp32"])
+def test_diagonal_metric_pool(rr, prec):
+    """Standardise-only metric: same kernels on the column-scaled covariates."""
+    say(f"diagonal metric pool {prec}")
+    rng = np.random.default_rng(77)
+    X = rng.standard_normal((300, 40)) @ rng.standard_normal((40, 40)) * rng.uniform(0.1, 10.0, 40)
+    pr = rr.PREC_SPLIT_BF16 if prec == "split" else rr.PREC_FP32
+    P = rr.rr_prepare(dev(X), 120, 1e-3, metric=rr.METRIC_DIAGONAL)
+    keys, M, flags = rr.rr_draw_balance(P, 99, 0, 20_000, rr.MODE_QUANTILE, 0.01, pr)
+    acc, Macc, Mall = pipeline.draw_balance(X, 120, 1e-3, 99, 0, 20_000, "quantile", 0.01, metric="diagonal")
+    np.testing.assert_array_equal(u64(keys), acc)
+    Mg, fl = M.cpu().numpy(), flags.cpu().numpy().astype(bool)
+    np.testing.assert_allclose(Mg[fl], Macc[fl], rtol=1e-9)
+    np.testing.assert_allclose(Mg[~fl], Macc[~fl], rtol=1e-4)
+    # the FP64 recheck path agrees with the oracle on arbitrary draws, and differs from the
+    # whitened statistic on these correlated covariates
+    ks = np.arange(0, 20_000, 97, dtype=np.uint64)
+    _, _, m64 = rr.rr_balance_keys(P, 99, keys_t(ks), pr)
+    np.testing.assert_allclose(m64.cpu().numpy(), Mall[ks.astype(np.int64)], rtol=1e-9)
+    Mmah = pipeline.balance_of_keys(X, 120, 1e-3, 99, ks)
+    assert np.max(np.abs(Mmah - Mall[ks.astype(np.int64)]) / Mmah) > 1e-2
+

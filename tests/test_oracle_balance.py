@@ -98,3 +98,57 @@ def test_rank_deficient_pinv_is_constant():
 
 def test_exact_enumeration_count():
     assert comb(20, 10) == 184756
+
+
+# ---- diagonal (standardise-only) metric
+def all_M_metric(X, n1, metric, ridge_rel=0.0):
+    P = prep.prepare(X, n1, ridge_rel, metric)
+    W = assign.exact_assignments(X.shape[0], n1)
+    return W, balance.mahalanobis_batch(X, W, P["S_lam"]), P
+
+
+def test_diagonal_reduces_to_mahalanobis_for_one_covariate():
+    X = np.random.default_rng(20).standard_normal((12, 1))
+    _, Md, _ = all_M_metric(X, 5, "diagonal")
+    _, Mm, _ = all_M_metric(X, 5, "mahalanobis")
+    np.testing.assert_allclose(Md, Mm, rtol=1e-12)
+
+
+def test_diagonal_equals_mahalanobis_for_orthogonal_columns():
+    # centred columns of a Hadamard design are orthogonal, so S is diagonal
+    H = np.array([[1, 1, 1, 1], [1, -1, 1, -1], [1, 1, -1, -1], [1, -1, -1, 1]], dtype=float)
+    X = np.kron(H, np.ones((3, 1)))[:, 1:] * np.array([1.0, 2.5, 0.3])
+    _, Md, _ = all_M_metric(X, 6, "diagonal")
+    _, Mm, _ = all_M_metric(X, 6, "mahalanobis")
+    np.testing.assert_allclose(Md, Mm, rtol=1e-12, atol=1e-12)
+
+
+def test_diagonal_mean_over_all_assignments():
+    # each standardised mean difference has variance exactly 1 / scale over all assignments
+    X = np.random.default_rng(21).standard_normal((12, 4)) @ np.random.default_rng(22).standard_normal((4, 4))
+    _, M, P = all_M_metric(X, 6, "diagonal")
+    assert abs(M.mean() - 4.0) < 1e-12
+    _, M, P = all_M_metric(X, 6, "diagonal", ridge_rel=0.5)
+    S = np.diag(P["S"])
+    assert abs(M.mean() - np.sum(S / (S + P["lam"]))) < 1e-12
+
+
+def test_diagonal_scaling_invariant_not_rotation_invariant():
+    rng = np.random.default_rng(23)
+    X = rng.standard_normal((12, 3))
+    _, M, _ = all_M_metric(X, 6, "diagonal")
+    _, Ms, _ = all_M_metric(X * np.array([3.0, 0.1, 7.0]) + 5.0, 6, "diagonal")
+    np.testing.assert_allclose(Ms, M, rtol=1e-10)
+    Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    _, Mr, _ = all_M_metric(X @ Q, 6, "diagonal")
+    _, Mm, _ = all_M_metric(X, 6, "mahalanobis")
+    _, Mmr, _ = all_M_metric(X @ Q, 6, "mahalanobis")
+    np.testing.assert_allclose(Mmr, Mm, rtol=1e-10)
+    assert np.max(np.abs(Mr - M)) > 1e-3
+
+
+def test_diagonal_constant_column_is_singular():
+    X = np.random.default_rng(24).standard_normal((10, 3))
+    X[:, 1] = 2.0
+    with pytest.raises(prep.SingularCovariance):
+        prep.prepare(X, 5, 0.0, "diagonal")
