@@ -99,6 +99,7 @@ def run_batched(args, rr, inputs, np, torch):
     torch.cuda.synchronize()
     ms_per_step = 1000.0 * (time.perf_counter() - t0) / args.steps
     kernels = rr.rr_last_timing()["launches"]
+    band_total = rr.rr_last_timing()["band"]
     # per-pool launch sequences, one pass
     t1 = time.perf_counter()
     same = True
@@ -118,7 +119,7 @@ def run_batched(args, rr, inputs, np, torch):
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": args.workload, "num_problems": w["num_problems"], "num_draws": N, "q": q,
                    "step": "rr_draw_balance_batched (one graph launch)"},
-        "graph_gpu_ms_per_step": graph_ms / args.steps, "graph_kernels": kernels,
+        "graph_gpu_ms_per_step": graph_ms / args.steps, "graph_kernels": kernels, "guard_band_total": band_total,
         "mfma_tflops_over_graph": achieved, "frac_bf16_peak_over_graph": achieved / PEAK_BF16_TFLOPS,
         "per_pool_calls": {"ms": loop_ms, "draws_per_s": total / (loop_ms / 1000.0),
                            "batched_speedup": loop_ms / ms_per_step, "same_results_sampled": same},

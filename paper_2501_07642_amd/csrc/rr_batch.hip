@@ -32,6 +32,10 @@ namespace rr {
 constexpr int kFinishSort = 2048;              // accepted keys sorted in LDS per pool
 constexpr uint32_t kBatchBandCap = 1u << 14;   // guard-band entries per pool
 constexpr size_t kBitsBudget = size_t(1) << 30;   // bytes per bitmask round buffer
+// Recheck workgroups per pool: a pool's band (up to kBatchBandCap entries, large where M
+// hardly varies across draws, e.g. d >= n - 1 with a small ridge) is spread over this many
+// workgroups; workgroups past a small band exit at once.
+constexpr int kBatchRecheckWgs = 32;
 
 // Per-pool record of the acceptance stages (device).
 struct PoolRec {
@@ -452,7 +456,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         B.exec = nullptr;
         B.graph = nullptr;
         B.sig.clear();
-        const size_t nev = 2 * R * groups.size() + 2;
+        const size_t nev = 2 * R * groups.size() + 4;
         while (B.ev.size() < nev) {
             hipEvent_t e;
             RR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -461,6 +465,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         hipEvent_t* ready = B.ev.data();                          // [r][group]
         hipEvent_t* freed = B.ev.data() + R * groups.size();      // [r][group]
         hipEvent_t fork = B.ev[2 * R * groups.size()], join = B.ev[2 * R * groups.size() + 1];
+        hipEvent_t fork2 = B.ev[2 * R * groups.size() + 2], join2 = B.ev[2 * R * groups.size() + 3];
         int64_t kernels = 0;
         hipError_t e = hipStreamBeginCapture(B.s_main, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) {
@@ -503,10 +508,16 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
                            mode, q_or_a);
         check(hipGetLastError());
         ++kernels;
+        // the groups' rechecks are independent: alternate them over the two streams
+        check(hipEventRecord(fork2, B.s_main));
+        check(hipStreamWaitEvent(B.s_gen, fork2, 0));
         for (size_t gi = 0; gi < groups.size(); ++gi) {
-            check(launch_recheck_batch(groups[gi].S, d_rt + gpos[gi], (int)groups[gi].idx.size(), 2, B.s_main));
+            check(launch_recheck_batch(groups[gi].S, d_rt + gpos[gi], (int)groups[gi].idx.size(), kBatchRecheckWgs,
+                                       (gi & 1) ? B.s_gen : B.s_main));
             ++kernels;
         }
+        check(hipEventRecord(join2, B.s_gen));
+        check(hipStreamWaitEvent(B.s_main, join2, 0));
         hipLaunchKernelGGL(batch_finish_kernel, dim3((unsigned)nprob), dim3(1024), 0, B.s_main, d_pr, mode, q_or_a);
         check(hipGetLastError());
         ++kernels;
