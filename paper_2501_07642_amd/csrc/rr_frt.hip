@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void frt_stats_kernel(const uint64_t* keys, ui
                                                         const int64_t* meta, const uint32_t* obs_bits,
                                                         int64_t* alpha, int64_t* beta, uint32_t* out_bits) {
     __shared__ uint32_t sbits[4][8 * kMaxS];
-    __shared__ uint2 slist[4][64];
+    __shared__ uint2 slist[4][128];
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int nw = (n + 31) / 32;
     for (uint64_t k = (uint64_t)blockIdx.x * 4 + wave; k < K; k += (uint64_t)gridDim.x * 4) {
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void frt_stats_kernel(const uint64_t* keys, ui
                 sbits[wave][1] = (uint32_t)(m >> 32);
             }
         } else {
-            gen_mc_bits<S>(seed, keys[k], n, n1, slist[wave], sbits[wave]);
+            gen_mc_bits_fixed<S>(seed, keys[k], n, n1, slist[wave], sbits[wave]);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();

@@ -12,7 +12,7 @@ namespace rr {
 
 template <int S, bool EXACT>
 __global__ __launch_bounds__(256) void gen_kernel(GenArgs g) {
-    __shared__ uint2 slist[4][64];
+    __shared__ uint2 slist[4][128];
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave, nw = (uint64_t)gridDim.x * 4;
     if constexpr (EXACT) {
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void gen_kernel(GenArgs g) {
     } else {
         for (uint64_t idx = gw; idx < g.num; idx += nw) {
             const uint64_t key = g.keylist ? g.keylist[idx] : g.key_begin + idx;
-            gen_mc_bits<S>(g.seed, key, g.n, g.n1, slist[wave], g.out + idx * (8 * S));
+            gen_mc_bits_fixed<S>(g.seed, key, g.n, g.n1, slist[wave], g.out + idx * (8 * S));
             __builtin_amdgcn_wave_barrier();
         }
     }
@@ -56,13 +56,13 @@ hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t
 // idx / per (draw idx % per of the pool's range).  One wave per draw.
 template <int S>
 __global__ __launch_bounds__(256) void gen_batch_kernel(const GenArgs* tab, uint64_t total, uint64_t per) {
-    __shared__ uint2 slist[4][64];
+    __shared__ uint2 slist[4][128];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave, nw = (uint64_t)gridDim.x * 4;
     for (uint64_t idx = gw; idx < total; idx += nw) {
         const uint64_t p = idx / per, i = idx - p * per;
         const GenArgs& g = tab[p];
-        gen_mc_bits<S>(g.seed, g.key_begin + i, g.n, g.n1, slist[wave], g.out + i * (8 * S));
+        gen_mc_bits_fixed<S>(g.seed, g.key_begin + i, g.n, g.n1, slist[wave], g.out + i * (8 * S));
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void regen_kernel(const uint64_t* keys, uint64
                                                     int n, int n1, const uint64_t* binom,
                                                     uint32_t* out, int nw) {
     __shared__ uint32_t sbits[4][8 * kMaxS];
-    __shared__ uint2 slist[4][64];
+    __shared__ uint2 slist[4][128];
     const int wave = threadIdx.x >> 6, lane = lane_id();
     for (uint64_t k = (uint64_t)blockIdx.x * 4 + wave; k < K; k += (uint64_t)gridDim.x * 4) {
         if constexpr (EXACT) {
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void regen_kernel(const uint64_t* keys, uint64
                 sbits[wave][1] = (uint32_t)(m >> 32);
             }
         } else {
-            gen_mc_bits<S>(seed, keys[k], n, n1, slist[wave], sbits[wave]);
+            gen_mc_bits_fixed<S>(seed, keys[k], n, n1, slist[wave], sbits[wave]);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();

@@ -185,18 +185,23 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
+__device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                             uint32_t k0, uint32_t k1) {
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+}
+
 __device__ __forceinline__ void philox_block(uint32_t& c0, uint32_t& c1, uint32_t& c2,
                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
-        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
+        philox_round(c0, c1, c2, c3, k0, k1);
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
     }
@@ -237,29 +242,62 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // values), then bisect, so the loop ends after at most 4 + 32 steps for any input.  The
 // <= 64 values left in the bracket are ranked in LDS; values equal to u* are taken in unit
 // order.  Output: bitmask words (bit i%32 of word i/32), written by lane 0 to `out` (8 S
-// words).  `list` is a wave-private 64-entry LDS array.
-template <int S>
+// words).  `list` is a wave-private 128-entry LDS array (64 slots for the bracket values,
+// 64 spare slots that take the non-members' stores).
+//
+// C > 0 fixes the number of 256-unit chunks (ceil(n / 256)) at compile time: the per-chunk
+// validity tests fold away and only the last chunk keeps a runtime lane mask; C = 0 takes
+// it from n at run time.
+template <int S, int C = 0>
 __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint2* list,
                                             uint32_t* out) {
+    static_assert(C >= 0 && C <= S, "chunk count within the bitmask layout");
     const int lane = lane_id();
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const uint32_t blo = (uint32_t)key, bhi = (uint32_t)(key >> 32);
-    const int chunks = (n + kUnitsPerChunk - 1) / kUnitsPerChunk;
+    const int chunks = C > 0 ? C : (n + kUnitsPerChunk - 1) / kUnitsPerChunk;
     uint32_t u[S][4];
     uint64_t vm[S][4];   // lanes holding a unit < n (wave-uniform)
+    if constexpr (C > 0) {
+        // all C blocks advance round by round: C independent multiply chains per lane
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            u[s][0] = 64u * s + lane;
+            u[s][1] = 0u;
+            u[s][2] = blo;
+            u[s][3] = bhi;
+        }
+        uint32_t ka = k0, kb = k1;
+#pragma unroll
+        for (int r = 0; r < 10; ++r) {
+#pragma unroll
+            for (int s = 0; s < C; ++s) philox_round(u[s][0], u[s][1], u[s][2], u[s][3], ka, kb);
+            ka += kPhiloxW0;
+            kb += kPhiloxW1;
+        }
+#pragma unroll
+        for (int s = C; s < S; ++s) u[s][0] = u[s][1] = u[s][2] = u[s][3] = 0u;
+    }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        if (s < chunks) {
-            uint32_t c0 = 64u * s + lane, c1 = 0, c2 = blo, c3 = bhi;
-            philox_block(c0, c1, c2, c3, k0, k1);
-            u[s][0] = c0; u[s][1] = c1; u[s][2] = c2; u[s][3] = c3;
-        } else {
-            u[s][0] = u[s][1] = u[s][2] = u[s][3] = 0u;
+        if constexpr (C == 0) {
+            if (s < chunks) {
+                uint32_t c0 = 64u * s + lane, c1 = 0, c2 = blo, c3 = bhi;
+                philox_block(c0, c1, c2, c3, k0, k1);
+                u[s][0] = c0; u[s][1] = c1; u[s][2] = c2; u[s][3] = c3;
+            } else {
+                u[s][0] = u[s][1] = u[s][2] = u[s][3] = 0u;
+            }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int left = n - 256 * s - 64 * r;
-            vm[s][r] = left >= 64 ? ~0ull : (left <= 0 ? 0ull : ((1ull << left) - 1));
+            if (C > 0 && s < C - 1)
+                vm[s][r] = ~0ull;                        // a full chunk
+            else if (C > 0 && s >= C)
+                vm[s][r] = 0ull;                         // past the last chunk
+            else
+                vm[s][r] = left >= 64 ? ~0ull : (left <= 0 ? 0ull : ((1ull << left) - 1));
         }
     }
     auto count_below = [&](uint64_t p) -> int {   // #{valid u < p}, p in [0, 2^32]
@@ -316,12 +354,13 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
                     const bool f = (uint64_t)(u[s][r] - l32) < span;   // lo <= u < hi
                     const uint64_t bm = ballot(f) & vm[s][r];
                     if (bm) {
-                        if ((bm >> lane) & 1ull) {
-                            const int pos = base + (int)__builtin_amdgcn_mbcnt_hi(
-                                                       (uint32_t)(bm >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
-                            list[pos] = make_uint2(u[s][r], 0u);
-                        }
+                        // members go to slots base.., the other lanes to their own spare slot
+                        const int pos = ((bm >> lane) & 1ull)
+                                            ? base + (int)__builtin_amdgcn_mbcnt_hi(
+                                                         (uint32_t)(bm >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u))
+                                            : 64 + lane;
+                        list[pos] = make_uint2(u[s][r], 0u);
                         base += __builtin_popcountll(bm);
                     }
                 }
@@ -395,6 +434,30 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
             reinterpret_cast<uint4*>(out + 8 * s)[0] = make_uint4(w[0], w[1], w[2], w[3]);
             reinterpret_cast<uint4*>(out + 8 * s)[1] = make_uint4(w[4], w[5], w[6], w[7]);
         }
+    }
+}
+
+// gen_mc_bits with the chunk count of n fixed at compile time (S / 2 < chunks <= S).
+template <int S>
+__device__ __forceinline__ void gen_mc_bits_fixed(uint64_t seed, uint64_t key, int n, int n1, uint2* list,
+                                                  uint32_t* out) {
+    const int chunks = (n + kUnitsPerChunk - 1) / kUnitsPerChunk;
+    if constexpr (S == 1) {
+        gen_mc_bits<1, 1>(seed, key, n, n1, list, out);
+    } else if constexpr (S == 2) {
+        gen_mc_bits<2, 2>(seed, key, n, n1, list, out);
+    } else if constexpr (S == 4) {
+        if (chunks == 4) gen_mc_bits<4, 4>(seed, key, n, n1, list, out);
+        else gen_mc_bits<4, 3>(seed, key, n, n1, list, out);
+    } else if constexpr (S == 8) {
+        switch (chunks) {
+            case 8: gen_mc_bits<8, 8>(seed, key, n, n1, list, out); break;
+            case 7: gen_mc_bits<8, 7>(seed, key, n, n1, list, out); break;
+            case 6: gen_mc_bits<8, 6>(seed, key, n, n1, list, out); break;
+            default: gen_mc_bits<8, 5>(seed, key, n, n1, list, out); break;
+        }
+    } else {
+        gen_mc_bits<S, 0>(seed, key, n, n1, list, out);
     }
 }
 

@@ -21,7 +21,7 @@ constexpr int kRecheckTile = 16;
 
 struct RecheckShared {
     uint32_t* bits;        // [kRecheckTile][8 S + 1]
-    uint2* list;           // [4][64]
+    uint2* list;           // [4][128]
     double* red;           // [4][kRecheckTile]
 };
 
@@ -48,7 +48,7 @@ __device__ __forceinline__ void recheck_run(const RecheckArgs& a, uint32_t wg, u
                         bt[1] = (uint32_t)(m >> 32);
                     }
                 } else {
-                    gen_mc_bits<S>(a.seed, a.keys[e0 + t], a.n, a.n1, sh.list + 64 * wave, bt);
+                    gen_mc_bits_fixed<S>(a.seed, a.keys[e0 + t], a.n, a.n1, sh.list + 128 * wave, bt);
                 }
             } else {
                 for (int w = lane; w < 8 * S; w += 64) bt[w] = 0u;
@@ -105,7 +105,7 @@ __device__ __forceinline__ void recheck_run(const RecheckArgs& a, uint32_t wg, u
 template <int S, bool EXACT>
 __device__ __forceinline__ void recheck_dispatch(const RecheckArgs& a, uint32_t wg, uint32_t nwg) {
     __shared__ uint32_t bits[kRecheckTile * (8 * S + 1)];
-    __shared__ uint2 list[4 * 64];
+    __shared__ uint2 list[4 * 128];
     __shared__ double red[4 * kRecheckTile];
     const RecheckShared sh{bits, list, red};
     if (a.d <= 64)

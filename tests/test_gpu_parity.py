@@ -48,8 +48,10 @@ def keys_t(keys):
     return dev(np.asarray(keys, dtype=np.uint64).astype(np.int64))
 
 
-@pytest.mark.parametrize("n,n1", [(1, 0), (5, 2), (20, 10), (64, 31), (100, 50), (257, 100), (1000, 500),
-                                  (2000, 1000), (4096, 2048)])
+# one n per 256-unit chunk count 1..8 (the generators specialise on it) plus the largest n
+@pytest.mark.parametrize("n,n1", [(1, 0), (5, 2), (20, 10), (64, 31), (100, 50), (257, 100), (600, 300),
+                                  (1000, 500), (1100, 550), (1400, 699), (1700, 851), (2000, 1000),
+                                  (4096, 2048)])
 def test_regenerate_bits_exact(rr, n, n1):
     if n1 == 0:
         pytest.skip("n1 must be at least 1")
