@@ -291,6 +291,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             return P[x]->P.ks * P[x]->P.ncb > P[y]->P.ks * P[y]->P.ncb;
         });
         g.tune = tune_for(P[g.idx[0]]->P, precision, false, N * (uint64_t)g.idx.size(), B.s_main);
+        g.tune.gen_wg = std::min(g.tune.gen_wg, gen_wg_fit(precision, S, g.tune.db, true));
         g.tile = contract_tile(precision, S, g.tune.db);
         groups.push_back(g);
     }

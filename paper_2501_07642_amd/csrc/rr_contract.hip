@@ -42,7 +42,9 @@ __device__ __forceinline__ uint4 expand_bf16(uint32_t x) {
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 template <int PREC, int NW, int CB, int DB, int S, bool BATCH>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 2)))
+// 8-wave tiles: at most 168 registers per wave (two waves per SIMD, 336 of the 512 registers),
+// which leaves three 64-register generation waves per SIMD beside them.
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 3 : NW / 2)))
 void contract_kernel(ContractArgs a0) {
     constexpr int TILE = NW * 32 * DB;
     constexpr int WSTR = 8 * S + 1;                       // +1: 32 draws hit 32 banks
@@ -243,8 +245,8 @@ void contract_kernel(ContractArgs a0) {
 
 // Tile shapes: covariate blocks per chunk (CB) and 32-draw blocks per wave (DB).  Split
 // BF16: 8 waves (two per SIMD, so one wave's bit expansion on the VALU overlaps the other's
-// MFMA), each with 2 x DB accumulator blocks of 32x32 (<= 128 registers, leaving room for
-// the generation kernel's waves); FP32: 4 waves of 2 x DB blocks plus a per-K-step block
+// MFMA), each with 2 x DB accumulator blocks of 32x32 (<= 168 registers, leaving room for
+// three generation waves per SIMD); FP32: 4 waves of 2 x DB blocks plus a per-K-step block
 // set.  The default DB is 2 where the tile's bitmasks fit in LDS beside the operand stages;
 // the autotuner may pick 1.  Per-draw arithmetic (and so every M32) does not depend on NW
 // or DB, only on CB.
@@ -305,6 +307,42 @@ hipError_t launch_contract(int S, int prec, int db, bool batch, const ContractAr
     return batch ? launch_contract_p<RR_PREC_FP32, true>(S, db, a, grid, st)
                  : launch_contract_p<RR_PREC_FP32, false>(S, db, a, grid, st);
 }
+
+// Vector registers per lane and waves per workgroup of a contraction tile (0 if unknown).
+template <int PREC, int S, int DB, bool BATCH>
+static int contract_vgprs_t() {
+    if constexpr (lds_for(PREC, S, DB) > kMaxLds) {
+        return 0;
+    } else {
+        hipFuncAttributes fa{};
+        auto k = contract_kernel<PREC, nw_for(PREC, S), kCB, DB, S, BATCH>;
+        return hipFuncGetAttributes(&fa, (const void*)k) == hipSuccess ? fa.numRegs : 0;
+    }
+}
+
+template <int PREC, bool BATCH>
+static int contract_vgprs_p(int S, int db) {
+    switch (S) {
+#define RR_CASE(SV) \
+    case SV: return db == 1 ? contract_vgprs_t<PREC, SV, 1, BATCH>() : contract_vgprs_t<PREC, SV, 2, BATCH>();
+        RR_CASE(1)
+        RR_CASE(2)
+        RR_CASE(4)
+        RR_CASE(8)
+        RR_CASE(16)
+#undef RR_CASE
+    }
+    return 0;
+}
+
+int contract_kernel_vgprs(int prec, int S, int db, bool batch) {
+    if (db == 0) db = db_default(prec, S);
+    if (!contract_db_ok(prec, S, db)) return 0;
+    if (prec == RR_PREC_SPLIT_BF16)
+        return batch ? contract_vgprs_p<RR_PREC_SPLIT_BF16, true>(S, db) : contract_vgprs_p<RR_PREC_SPLIT_BF16, false>(S, db);
+    return batch ? contract_vgprs_p<RR_PREC_FP32, true>(S, db) : contract_vgprs_p<RR_PREC_FP32, false>(S, db);
+}
+int contract_waves(int prec, int S) { return nw_for(prec, S); }
 
 int contract_tile(int prec, int S, int db) {
     if (db == 0) db = db_default(prec, S);

@@ -10,8 +10,10 @@
 
 namespace rr {
 
+// Up to 1024 units the generation waves are held to 64 registers (occupancy 8), so three of
+// them fit on every SIMD beside two contraction waves of up to 168 registers.
 template <int S, bool EXACT>
-__global__ __launch_bounds__(256) void gen_kernel(GenArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 8 : 1))) void gen_kernel(GenArgs g) {
     __shared__ uint2 slist[4][128];
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave, nw = (uint64_t)gridDim.x * 4;
@@ -55,7 +57,8 @@ hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t
 // Batched generation over a table of pools: global draw index idx belongs to pool
 // idx / per (draw idx % per of the pool's range).  One wave per draw.
 template <int S>
-__global__ __launch_bounds__(256) void gen_batch_kernel(const GenArgs* tab, uint64_t total, uint64_t per) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 8 : 1))) void gen_batch_kernel(
+    const GenArgs* tab, uint64_t total, uint64_t per) {
     __shared__ uint2 slist[4][128];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave, nw = (uint64_t)gridDim.x * 4;
@@ -79,6 +82,26 @@ hipError_t launch_gen_batch(int S, const GenArgs* tab, uint64_t nprob, uint64_t 
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Vector registers per lane of a Monte Carlo generation kernel (0 if unknown).
+int gen_kernel_vgprs(int S, bool batch) {
+    hipFuncAttributes fa{};
+    hipError_t e = hipErrorInvalidValue;
+    switch (S) {
+#define RR_CASE(SV)                                                                              \
+    case SV:                                                                                     \
+        e = batch ? hipFuncGetAttributes(&fa, (const void*)gen_batch_kernel<SV>)                 \
+                  : hipFuncGetAttributes(&fa, (const void*)gen_kernel<SV, false>);               \
+        break;
+        RR_CASE(1)
+        RR_CASE(2)
+        RR_CASE(4)
+        RR_CASE(8)
+        RR_CASE(16)
+#undef RR_CASE
+    }
+    return e == hipSuccess ? fa.numRegs : 0;
 }
 
 int pow2_chunks(int n) {

@@ -121,8 +121,9 @@ struct Tune {
     int db;
     int gen_wg;
 };
-// Generation workgroups per CU by default: three 4-wave workgroups (<= 80 VGPRs per wave) fit
-// beside one 8-wave contraction workgroup (128 VGPRs per wave, up to ~131 KB LDS) on every CU.
+// Generation workgroups per CU by default: three 4-wave workgroups (<= 64 VGPRs per wave up to
+// 1024 units) fit beside one 8-wave contraction workgroup (<= 168 VGPRs per wave, up to ~131 KB
+// LDS) on every CU.
 constexpr int kGenWgPerCu = 3;
 
 // Rigorous error-bound constants of the FP32 contraction of a problem (see rr_select.hip).
@@ -155,6 +156,10 @@ hipError_t launch_contract(int S, int prec, int db, bool batch, const ContractAr
 int contract_tile(int prec, int S, int db);
 bool contract_db_ok(int prec, int S, int db);
 int contract_db_default(int prec, int S);
+int contract_kernel_vgprs(int prec, int S, int db, bool batch);
+int contract_waves(int prec, int S);
+int gen_kernel_vgprs(int S, bool batch);
+int gen_wg_fit(int prec, int S, int db, bool batch);
 int draw_cb(int prec, int S);
 hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hipStream_t st);
 hipError_t launch_recheck_batch(int S, const RecheckArgs* tab, int nprob, int gx, hipStream_t st);
@@ -163,7 +168,7 @@ int device_cus(int dev);
 const uint64_t* binom_table(int dev);
 Bound bound_constants(const Problem& P, int prec);
 ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b);
-Tune tune_default(int prec, int S);
+Tune tune_default(int prec, int S, bool batch);
 Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t st);
 rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begin, uint64_t N, int mode,
                         double q_or_a, int prec, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
@@ -185,10 +190,19 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
+// 32 x 32 -> 64-bit product in one v_mad_u64_u32 (left to itself the compiler splits some
+// products into separate quarter-rate v_mul_lo_u32 / v_mul_hi_u32 instructions).
+__device__ __forceinline__ uint64_t mul_wide(uint32_t a, uint32_t b) {
+    uint64_t r, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(r), "=s"(carry) : "v"(a), "s"(b));
+    (void)carry;
+    return r;
+}
+
 __device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
                                              uint32_t k0, uint32_t k1) {
-    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
-    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+    const uint64_t p0 = mul_wide(c0, kPhiloxM0);
+    const uint64_t p1 = mul_wide(c2, kPhiloxM1);
     const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
     const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
     c1 = (uint32_t)p1;
@@ -236,10 +250,10 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // i = 256 s + 64 r + lane reads word r of Philox block 64 s + lane under counter
 // (block, 0, lo32(key), hi32(key)) and the pool seed as Philox key.
 //
-// Selection (exact): the n1-th smallest value u* is bracketed by [lo, hi) with
-// #{u < lo} < n1 <= #{u < hi}; counts come from wave ballots.  Pivots interpolate inside
+// Selection (exact): the n1-th smallest value u* is bracketed by [lo, hi] with
+// #{u < lo} < n1 <= #{u <= hi}; counts come from wave ballots.  Pivots interpolate inside
 // the bracket for the first steps (unit keys are uniform, so two or three steps leave a few
-// values), then bisect, so the loop ends after at most 4 + 32 steps for any input.  The
+// values), then bisect, so the loop ends after at most 4 + 33 steps for any input.  The
 // <= 64 values left in the bracket are ranked in LDS; values equal to u* are taken in unit
 // order.  Output: bitmask words (bit i%32 of word i/32), written by lane 0 to `out` (8 S
 // words).  `list` is a wave-private 128-entry LDS array (64 slots for the bracket values,
@@ -300,9 +314,7 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
                 vm[s][r] = left >= 64 ? ~0ull : (left <= 0 ? 0ull : ((1ull << left) - 1));
         }
     }
-    auto count_below = [&](uint64_t p) -> int {   // #{valid u < p}, p in [0, 2^32]
-        if (p > 0xFFFFFFFFull) return n;
-        const uint32_t pv = (uint32_t)p;
+    auto count_below = [&](uint32_t pv) -> int {   // #{valid u < pv}
         int c = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s)
@@ -312,46 +324,51 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
         return c;
     };
 
-    uint64_t lo = 0, hi = 1ull << 32;
+    // Bracket [lo, hi] (inclusive, 32-bit) around the n1-th smallest value u*:
+    // #{u < lo} = clo < n1 <= chi = #{u <= hi}.  A pivot p in (lo, hi] with c = #{u < p}
+    // moves lo to p (c < n1) or hi to p - 1 (c >= n1).
+    uint32_t lo = 0u, hi = 0xFFFFFFFFu;
     int clo = 0, chi = n;
     // stop at <= 8 bracket values after a few cheap counts, at <= 64 after many
-    for (int it = 0; (chi - clo > 64 || (chi - clo > 8 && it < 6)) && hi - lo > 1; ++it) {
-        uint64_t p;
+    for (int it = 0; (chi - clo > 64 || (chi - clo > 8 && it < 6)) && lo < hi; ++it) {
+        const uint32_t span = hi - lo;
+        uint32_t off;
         if (it < 4) {
-            const float f = (float)(n1 - clo) / (float)(chi - clo);
-            p = lo + (uint64_t)(f * (float)(hi - lo));
+            // interpolate: unit keys are uniform, so u* sits near the fraction (n1 - clo) / (chi - clo)
+            const float f = (float)(n1 - clo) * __builtin_amdgcn_rcpf((float)(chi - clo));
+            off = (uint32_t)fminf(fmaxf(f * (float)span, 0.0f), 4294967040.0f);
         } else {
-            p = lo + ((hi - lo) >> 1);
+            off = (span >> 1) + 1u;
         }
-        p = p <= lo ? lo + 1 : (p >= hi ? hi - 1 : p);
+        off = __builtin_amdgcn_readfirstlane(off);
+        const uint32_t p = off == 0u ? lo + 1u : (off >= span ? hi : lo + off);
         const int c = count_below(p);
         if (c < n1) {
             lo = p;
             clo = c;
         } else {
-            hi = p;
+            hi = p - 1u;
             chi = c;
         }
     }
 
     uint32_t ustar;
     int take, eq_total;
-    if (hi - lo == 1) {
-        // every value in the bracket equals lo
-        ustar = (uint32_t)lo;
+    if (lo == hi) {
+        // the bracket holds one value
+        ustar = lo;
         take = n1 - clo;
         eq_total = chi - clo;
     } else {
         // collect the <= 64 bracket values, rank them
-        const uint32_t l32 = (uint32_t)lo;
-        const uint64_t span = hi - lo;
+        const uint32_t span = hi - lo;
         int base = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (s < chunks) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const bool f = (uint64_t)(u[s][r] - l32) < span;   // lo <= u < hi
+                    const bool f = (u[s][r] - lo) <= span;   // lo <= u <= hi
                     const uint64_t bm = ballot(f) & vm[s][r];
                     if (bm) {
                         // members go to slots base.., the other lanes to their own spare slot

@@ -1,8 +1,8 @@
 // Autotuner of the draw pipeline's launch configuration.
 //
 // Tunables: the contraction tile (db = 32-draw blocks per wave, 1 or 2, where the tile's
-// bitmasks fit in LDS) and the generation kernel's workgroups per CU (2, 3 or 4, which sets
-// how much of each CU the generation waves share with the contraction).  Neither changes any
+// bitmasks fit in LDS) and the generation kernel's workgroups per CU (2 up to the number that
+// fits beside one contraction workgroup by registers, at most 4).  Neither changes any
 // result: per-draw arithmetic depends only on the covariate chunking, which is fixed.
 //
 // Buckets: (precision, S = 256-unit chunks per draw, floor(log2(ks * ncb))), i.e. the
@@ -27,7 +27,22 @@
 
 namespace rr {
 
-Tune tune_default(int prec, int S) { return Tune{contract_db_default(prec, S), kGenWgPerCu}; }
+// Generation workgroups (4 waves, one per SIMD) that fit on a CU beside one contraction
+// workgroup, by vector registers: a SIMD holds 512 per lane, allocated in steps of 8.  If the
+// generation kernel takes more, the contraction workgroup cannot start on that CU until the
+// persistent generation grid has drained, and the two kernels no longer overlap.
+int gen_wg_fit(int prec, int S, int db, bool batch) {
+    auto r8 = [](int v) { return (v + 7) & ~7; };
+    const int c = contract_kernel_vgprs(prec, S, db, batch), g = gen_kernel_vgprs(S, batch);
+    if (c <= 0 || g <= 0) return kGenWgPerCu;
+    const int free_regs = 512 - (contract_waves(prec, S) / 4) * r8(c);
+    return std::max(1, std::min(4, free_regs / r8(g)));
+}
+
+Tune tune_default(int prec, int S, bool batch) {
+    const int db = contract_db_default(prec, S);
+    return Tune{db, std::min(kGenWgPerCu, gen_wg_fit(prec, S, db, batch))};
+}
 
 namespace {
 
@@ -104,13 +119,18 @@ void save_file() {
 }  // namespace
 
 Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t st) {
-    const Tune def = tune_default(prec, P.S);
+    const Tune def = tune_default(prec, P.S, false);
     if (exact || !tuning_enabled()) return def;
     std::lock_guard<std::mutex> g(g_mu);
     if (!g_loaded) load_file();
     const Key key(prec, P.S, cost_log2(P));
     auto it = g_cache.find(key);
-    if (it != g_cache.end()) return it->second.t;
+    if (it != g_cache.end()) {
+        // entries read from a file may come from another build: keep them within the fit
+        Tune t = it->second.t;
+        t.gen_wg = std::min(t.gen_wg, gen_wg_fit(prec, P.S, t.db, false));
+        return t;
+    }
     if (work_draws < (1u << 20)) return def;
 
     // probe pool: ~2^42 MFMA flops, 2^18 .. 2^20 draws
@@ -129,7 +149,8 @@ Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t
     double best_ms = INFINITY;
     for (int db = 1; db <= 2; ++db) {
         if (!contract_db_ok(prec, P.S, db)) continue;
-        for (int gw = 2; gw <= 4; ++gw) {
+        const int fit = gen_wg_fit(prec, P.S, db, false);
+        for (int gw = std::min(2, fit); gw <= fit; ++gw) {
             const Tune t{db, gw};
             double ms = INFINITY;
             for (int rep = 0; rep < 3; ++rep) {
