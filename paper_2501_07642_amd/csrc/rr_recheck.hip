@@ -1,7 +1,8 @@
 // FP64 recomputation of M for draws in the guard band (and for rr_balance_keys).
 //
 // M = n / (n1 n0) ||G||^2 with G = sum_{i in T} X~_i (section 2.2; Appendix A remark), in
-// FP64 on the whitened covariates.
+// FP64 on the whitened covariates.  Exactly representable 0/1 weights make the FP64 matrix
+// product W X~ the same sums, accumulated with FP64 roundings.
 #include <algorithm>
 
 #include "rr_internal.h"
@@ -9,15 +10,16 @@
 namespace rr {
 
 // ---------------------------------------------------------------------------------------
-// FP64 recomputation of M for listed draws: 16 draws per workgroup tile.  The four waves
-// regenerate the treated sets into LDS; the threads then add the whitened rows of treated
-// units in ascending unit order, covariates split over the threads in column groups of CW
-// (row reads are coalesced and shared by the draws), and ||G||^2 is reduced per draw in a
-// fixed order.  The column-group width follows d so that few lanes idle:
-//   CW = 1024: every thread owns 4 columns and all 16 draws;
-//   CW = 256:  every thread owns 1 column and all 16 draws;
-//   CW = 64:   wave q owns draws 4q .. 4q+3, every lane 1 column.
+// FP64 recomputation of M for listed draws, 16 draws per workgroup tile, as the dense product
+// G (16 draws x d) = W (16 x n, 0/1) X~ (n x d) on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: A lane l holds W[draw l % 16][unit 4k + l / 16], B lane l holds
+// X~[unit 4k + l / 16][column l % 16], result item r of lane l is G[draw 4r + l / 16][column
+// l % 16]).  The four waves regenerate the treated sets into LDS, then split the 16-column
+// blocks; each wave adds G^2 of its blocks per draw and the partial sums are reduced in a fixed
+// order (16 lanes, then the four waves), so the value does not depend on the launch shape.
 constexpr int kRecheckTile = 16;
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 struct RecheckShared {
     uint32_t* bits;        // [kRecheckTile][8 S + 1]
@@ -25,16 +27,14 @@ struct RecheckShared {
     double* red;           // [4][kRecheckTile]
 };
 
-template <int S, bool EXACT, int CW>
+template <int S, bool EXACT>
 __device__ __forceinline__ void recheck_run(const RecheckArgs& a, uint32_t wg, uint32_t nwg, RecheckShared sh) {
     constexpr int WS = 8 * S + 1;
-    constexpr int TW = CW < 256 ? CW : 256;                 // threads across one column group row
-    constexpr int CPT = CW / TW;                            // columns per thread
-    constexpr int DT = CW < 256 ? kRecheckTile / 4 : kRecheckTile;   // draws per thread
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    const int d0 = CW < 256 ? DT * wave : 0;                // first draw of this thread
-    const int c0 = tid % TW;
+    const int g = lane >> 4, c = lane & 15;
     const uint32_t cnt = *a.count;
+    const int ncolb = (a.d + 15) / 16;
+    const int nk = (a.n + 31) / 32;                 // 32-unit words of a bitmask
     for (uint32_t e0 = wg * kRecheckTile; e0 < cnt; e0 += nwg * kRecheckTile) {
         const int nt = (int)min<uint32_t>(kRecheckTile, cnt - e0);
         for (int t = wave; t < kRecheckTile; t += 4) {
@@ -58,45 +58,39 @@ __device__ __forceinline__ void recheck_run(const RecheckArgs& a, uint32_t wg, u
         }
         for (int e = tid; e < 4 * kRecheckTile; e += blockDim.x) sh.red[e] = 0.0;
         __syncthreads();
-        double part[DT];
+        double part[4] = {0.0, 0.0, 0.0, 0.0};
+        const uint32_t* mybits = sh.bits + c * WS;     // draw c of the tile (A rows)
+        for (int cbk = wave; cbk < ncolb; cbk += 4) {
+            const int col = 16 * cbk + c;
+            const bool cval = col < a.d;
+            const double* xcol = a.X64 + (cval ? col : 0);
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int kw = 0; kw < nk; ++kw) {
+                // 32 units = 8 K steps of 4; bitmask bits past n are zero
+                const uint32_t word = mybits[kw];
 #pragma unroll
-        for (int t = 0; t < DT; ++t) part[t] = 0.0;
-        for (int cg = 0; cg < a.d; cg += CW) {
-            double G[DT][CPT];
-#pragma unroll
-            for (int t = 0; t < DT; ++t)
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) G[t][c] = 0.0;
-            for (int i = 0; i < a.n; ++i) {
-                double x[CPT];
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) {
-                    const int col = cg + c0 + TW * c;
-                    x[c] = col < a.d ? a.X64[(size_t)i * a.d + col] : 0.0;
-                }
-#pragma unroll
-                for (int t = 0; t < DT; ++t) {
-                    const uint32_t w = __builtin_amdgcn_readfirstlane(sh.bits[(d0 + t) * WS + (i >> 5)]);
-                    if ((w >> (i & 31)) & 1u) {
-#pragma unroll
-                        for (int c = 0; c < CPT; ++c) G[t][c] += x[c];
-                    }
+                for (int q = 0; q < 8; ++q) {
+                    const int unit = 32 * kw + 4 * q + g;
+                    const double av = ((word >> (4 * q + g)) & 1u) ? 1.0 : 0.0;
+                    const double bv = (cval && unit < a.n) ? xcol[(size_t)unit * a.d] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
                 }
             }
 #pragma unroll
-            for (int t = 0; t < DT; ++t)
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) part[t] = fma(G[t][c], G[t][c], part[t]);
+            for (int r = 0; r < 4; ++r) part[r] = fma(acc[r], acc[r], part[r]);
         }
+        // part[r] of lane (g, c): draw 4r + g, column c of this wave's blocks
 #pragma unroll
-        for (int t = 0; t < DT; ++t) {
-            const double v = wave_sum<double>(part[t]);
-            if (lane == 0) sh.red[wave * kRecheckTile + d0 + t] = v;
+        for (int r = 0; r < 4; ++r) {
+            double v = part[r];
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (c == 0) sh.red[wave * kRecheckTile + 4 * r + g] = v;
         }
         __syncthreads();
         if (tid < nt) {
-            const double* r = sh.red;
-            a.out[e0 + tid] = a.scale * ((r[tid] + r[kRecheckTile + tid]) + (r[2 * kRecheckTile + tid] + r[3 * kRecheckTile + tid]));
+            const double* rr = sh.red;
+            a.out[e0 + tid] = a.scale * ((rr[tid] + rr[kRecheckTile + tid]) + (rr[2 * kRecheckTile + tid] + rr[3 * kRecheckTile + tid]));
         }
         __syncthreads();
     }
@@ -108,12 +102,7 @@ __device__ __forceinline__ void recheck_dispatch(const RecheckArgs& a, uint32_t 
     __shared__ uint2 list[4 * 128];
     __shared__ double red[4 * kRecheckTile];
     const RecheckShared sh{bits, list, red};
-    if (a.d <= 64)
-        recheck_run<S, EXACT, 64>(a, wg, nwg, sh);
-    else if (a.d <= 256)
-        recheck_run<S, EXACT, 256>(a, wg, nwg, sh);
-    else
-        recheck_run<S, EXACT, 1024>(a, wg, nwg, sh);
+    recheck_run<S, EXACT>(a, wg, nwg, sh);
 }
 
 template <int S, bool EXACT>
