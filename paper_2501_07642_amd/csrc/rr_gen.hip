@@ -10,10 +10,11 @@
 
 namespace rr {
 
-// Up to 1024 units the generation waves are held to 64 registers (occupancy 8), so three of
-// them fit on every SIMD beside two contraction waves of up to 168 registers.
+// Register caps that keep three generation waves on every SIMD beside two contraction waves:
+// up to 1024 units 64 registers (beside contraction waves of up to 168), up to 2048 units 96
+// (beside the 1-block tiles of about 112; a few bytes spill).
 template <int S, bool EXACT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 8 : 1))) void gen_kernel(GenArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 8 : (S == 8 ? 5 : 1)))) void gen_kernel(GenArgs g) {
     __shared__ uint2 slist[4][128];
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave, nw = (uint64_t)gridDim.x * 4;
@@ -57,7 +58,7 @@ hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t
 // Batched generation over a table of pools: global draw index idx belongs to pool
 // idx / per (draw idx % per of the pool's range).  One wave per draw.
 template <int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 8 : 1))) void gen_batch_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 8 : (S == 8 ? 5 : 1)))) void gen_batch_kernel(
     const GenArgs* tab, uint64_t total, uint64_t per) {
     __shared__ uint2 slist[4][128];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
