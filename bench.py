@@ -141,7 +141,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this hot path runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "(the multi-GPU sharding of the path is not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
