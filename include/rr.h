@@ -124,7 +124,10 @@ double rr_problem_lambda(const rr_problem* p);
  *
  * Outputs (device, caller-allocated, `capacity` entries):
  *   d_keys   accepted keys, ascending;
- *   d_M      their M (the FP64 value when it was recomputed, else the FP32 value);
+ *   d_M      their M: the FP64 recomputation for draws of the guard band and, when d <= 64,
+ *            for every accepted draw (there the BF16 hi + lo representation of X~ limits the
+ *            FP32 value's relative accuracy to about 2^-17 sqrt(d / M)); else the FP32 value,
+ *            within 1e-4 relative;
  *   d_flags  optional (may be null): 1 where d_M holds the FP64 recomputation.
  *   h_count  host: number of accepted draws.
  * Errors: RR_E_ARG, RR_E_CAPACITY, RR_E_DEVICE.

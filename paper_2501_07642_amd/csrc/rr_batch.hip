@@ -321,7 +321,8 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     const size_t o_bk = take(8 * np * band_cap), o_bm = take(8 * np * band_cap), o_bw = take(np * band_cap);
     const size_t o_st = take(sizeof(AcceptState) * np);
     const size_t o_gt = take(sizeof(GenArgs) * np * R), o_ct = take(sizeof(ContractArgs) * np * R);
-    const size_t o_rt = take(sizeof(RecheckArgs) * np), o_pr = take(sizeof(PoolRec) * np);
+    const size_t o_rt = take(sizeof(RecheckArgs) * np), o_rta = take(sizeof(RecheckArgs) * np);
+    const size_t o_pr = take(sizeof(PoolRec) * np);
     if (off > B.ws_bytes) {
         if (B.exec) hipGraphExecDestroy(B.exec);
         if (B.graph) hipGraphDestroy(B.graph);
@@ -348,12 +349,14 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     GenArgs* d_gt = (GenArgs*)(base + o_gt);
     ContractArgs* d_ct = (ContractArgs*)(base + o_ct);
     RecheckArgs* d_rt = (RecheckArgs*)(base + o_rt);
+    RecheckArgs* d_rta = (RecheckArgs*)(base + o_rta);
     PoolRec* d_pr = (PoolRec*)(base + o_pr);
 
     // ---- tables: [round][group order] for generation / contraction; pool order elsewhere
     std::vector<GenArgs> gt(np * R);
     std::vector<ContractArgs> ct(np * R);
-    std::vector<RecheckArgs> rt(np);
+    std::vector<RecheckArgs> rt(np), rta(np);
+    bool any_refine = false;
     std::vector<PoolRec> pr(np);
     std::vector<size_t> gpos(groups.size());   // first table slot of each group within a round
     {
@@ -395,6 +398,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             ra.X64 = Q.X64;
             ra.keys = d_bk + (size_t)i * band_cap;
             ra.count = &d_st[i].band_count;
+            ra.cap = band_cap;
             ra.seed = seeds[i];
             ra.n = (int)Q.n;
             ra.n1 = (int)Q.n1;
@@ -402,6 +406,14 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             ra.scale = Q.scale;
             ra.out = d_bm + (size_t)i * band_cap;
             rt[gpos[gi] + j] = ra;
+            // small d: the draws accepted outright are recomputed in FP64 as well (cap 0 skips)
+            RecheckArgs rf = ra;
+            rf.keys = d_ak + (size_t)i * acc_cap;
+            rf.count = &d_st[i].acc_count;
+            rf.cap = Q.d <= kRefineMaxD ? acc_cap : 0u;
+            rf.out = d_am + (size_t)i * acc_cap;
+            rta[gpos[gi] + j] = rf;
+            any_refine = any_refine || Q.d <= kRefineMaxD;
             rt_order.push_back(i);
         }
     }
@@ -428,6 +440,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     RR_HIP(hipMemcpyAsync(d_gt, gt.data(), sizeof(GenArgs) * gt.size(), hipMemcpyHostToDevice, B.s_main));
     RR_HIP(hipMemcpyAsync(d_ct, ct.data(), sizeof(ContractArgs) * ct.size(), hipMemcpyHostToDevice, B.s_main));
     RR_HIP(hipMemcpyAsync(d_rt, rt.data(), sizeof(RecheckArgs) * rt.size(), hipMemcpyHostToDevice, B.s_main));
+    RR_HIP(hipMemcpyAsync(d_rta, rta.data(), sizeof(RecheckArgs) * rta.size(), hipMemcpyHostToDevice, B.s_main));
     RR_HIP(hipMemcpyAsync(d_pr, pr.data(), sizeof(PoolRec) * pr.size(), hipMemcpyHostToDevice, B.s_main));
     RR_HIP(hipStreamSynchronize(B.s_main));
 
@@ -516,6 +529,11 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             check(launch_recheck_batch(groups[gi].S, d_rt + gpos[gi], (int)groups[gi].idx.size(), kBatchRecheckWgs,
                                        (gi & 1) ? B.s_gen : B.s_main));
             ++kernels;
+            if (any_refine) {
+                check(launch_recheck_batch(groups[gi].S, d_rta + gpos[gi], (int)groups[gi].idx.size(),
+                                           kBatchRecheckWgs, (gi & 1) ? B.s_gen : B.s_main));
+                ++kernels;
+            }
         }
         check(hipEventRecord(join2, B.s_gen));
         check(hipStreamWaitEvent(B.s_main, join2, 0));

@@ -108,12 +108,18 @@ struct RecheckArgs {
     const double* X64;        // n x d, row-major
     const uint64_t* keys;     // keys of the draws
     const uint32_t* count;    // number of entries (device)
+    uint32_t cap;             // entries past cap are ignored (the lists hold cap entries)
     uint64_t seed;
     const uint64_t* binom;
     int n, n1, d;
     double scale;
     double* out;              // M64 per entry
 };
+
+// Up to this many covariates every accepted draw is reported with its FP64 M: the BF16
+// hi + lo representation error of X~ (2^-18 relative per entry) makes the FP32 value's
+// relative error about 2^-17 sqrt(d / M), which can pass 1e-4 only at small d and tiny M.
+constexpr int kRefineMaxD = 64;
 
 // Launch configuration of the draw pipeline, chosen by the autotuner per problem bucket:
 // draws per wave block of the contraction tile (db, 1 or 2) and generation workgroups per CU.

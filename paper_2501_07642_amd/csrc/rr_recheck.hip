@@ -32,7 +32,7 @@ __device__ __forceinline__ void recheck_run(const RecheckArgs& a, uint32_t wg, u
     constexpr int WS = 8 * S + 1;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
-    const uint32_t cnt = *a.count;
+    const uint32_t cnt = min(*a.count, a.cap);
     const int ncolb = (a.d + 15) / 16;
     const int nk = (a.n + 31) / 32;                 // 32-unit words of a bitmask
     for (uint32_t e0 = wg * kRecheckTile; e0 < cnt; e0 += nwg * kRecheckTile) {

@@ -184,6 +184,12 @@ __global__ void classify_kernel(const uint64_t* ck, const float* chi, const floa
     }
 }
 
+// flag[i] = 1 for i < min(*count, cap)
+__global__ void fill_flags_kernel(uint8_t* flag, const uint32_t* count, uint32_t cap) {
+    const uint32_t n = min(*count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) flag[i] = 1;
+}
+
 __global__ void cap_band_kernel(Ctl* ctl, uint32_t cap) {
     if (ctl->ac.band_count > cap) {
         ctl->overflow = 1;
@@ -584,6 +590,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
     ra.X64 = P.X64;
     ra.keys = w.band_key;
     ra.count = &w.ctl->ac.band_count;
+    ra.cap = band_cap;
     ra.seed = seed;
     ra.binom = binom;
     ra.n = (int)P.n;
@@ -592,6 +599,18 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
     ra.scale = P.scale;
     ra.out = w.band_m;
     RR_HIP(launch_recheck(P.S, exact, ra, (int)std::min<uint64_t>((hc.cand_count + 15) / 16 + 1, (uint64_t)device_cus(P.device) * 2), st));
+    if (P.d <= kRefineMaxD) {
+        // the draws accepted outright are reported with their FP64 values too
+        RecheckArgs rf = ra;
+        rf.keys = w.acc_key;
+        rf.count = &w.ctl->ac.acc_count;
+        rf.cap = acc_cap;
+        rf.out = w.acc_m;
+        RR_HIP(launch_recheck(P.S, exact, rf, (int)std::min<uint64_t>((std::min<uint64_t>(hc.cand_count, acc_cap) + 15) / 16 + 1,
+                                                                      (uint64_t)device_cus(P.device) * 2), st));
+        hipLaunchKernelGGL(fill_flags_kernel, dim3(64), dim3(256), 0, st, w.acc_flag, &w.ctl->ac.acc_count, acc_cap);
+        RR_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(band_accept_kernel, dim3(1), dim3(1024), 0, st, w.band_key, w.band_m, w.band_work, w.ctl,
                        mode, q_or_a, w.acc_key, w.acc_m, w.acc_flag, acc_cap);
     RR_HIP(hipGetLastError());
@@ -775,6 +794,7 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
         ra.X64 = P.X64;
         ra.keys = d_keys;
         ra.count = cnt;
+        ra.cap = k32;
         ra.seed = seed;
         ra.binom = binom;
         ra.n = (int)P.n;

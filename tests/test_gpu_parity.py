@@ -221,3 +221,28 @@ def test_diagonal_metric_pool(rr, prec):
     Mmah = pipeline.balance_of_keys(X, 120, 1e-3, 99, ks)
     assert np.max(np.abs(Mmah - Mall[ks.astype(np.int64)]) / Mmah) > 1e-2
 
+
+
+@pytest.mark.parametrize("n,d,N", [(3000, 40, 3000), (4096, 24, 2048)])
+def test_pool_large_n(rr, n, d, N):
+    """n above 2048: 16 chunks of 256 units, generated with a runtime chunk count."""
+    say(f"pool large n={n} d={d} N={N}")
+    X = inputs.gaussian_X(n, d, n + 3)
+    for prec in ("split", "fp32"):
+        _check_pool(rr, X, n // 2 - 7, 1e-3, 99, N, "quantile", 0.02, prec)
+
+
+@pytest.mark.parametrize("mode,qa", [("quantile", 0.003), ("threshold", 2.0)])
+def test_exact_enumeration_unbalanced(rr, mode, qa):
+    """All C(22, 6) = 74613 assignments of an unbalanced design (no M(w) = M(1 - w) pairs)."""
+    say(f"exact n=22 n1=6 {mode}")
+    X = inputs.gaussian_X(22, 4, 2201)
+    P = rr.rr_prepare(dev(X), 6, 0.0)
+    md = rr.MODE_QUANTILE if mode == "quantile" else rr.MODE_THRESHOLD
+    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32):
+        keys, M, flags = rr.rr_draw_exact(P, md, qa, prec)
+        acc, Macc, _ = pipeline.draw_exact(X, 6, 0.0, mode, qa)
+        np.testing.assert_array_equal(u64(keys), acc)
+        Mg, fl = M.cpu().numpy(), flags.cpu().numpy().astype(bool)
+        np.testing.assert_allclose(Mg[fl], Macc[fl], rtol=1e-9)
+        np.testing.assert_allclose(Mg[~fl], Macc[~fl], rtol=1e-4)
