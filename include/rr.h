@@ -49,7 +49,7 @@ typedef enum {
     RR_E_UNSUPPORTED = 7 /* shape beyond this build's limits (see call) */
 } rr_status;
 
-enum { RR_MODE_QUANTILE = 0, RR_MODE_THRESHOLD = 1 };
+enum { RR_MODE_QUANTILE = 0, RR_MODE_THRESHOLD = 1, RR_MODE_CHI2_QUANTILE = 2 };
 enum { RR_PREC_SPLIT_BF16 = 0, RR_PREC_FP32 = 1 };
 enum { RR_X_FP64 = 0, RR_X_FP32 = 1 };
 enum { RR_METRIC_MAHALANOBIS = 0, RR_METRIC_DIAGONAL = 1 };
@@ -114,6 +114,9 @@ double rr_problem_lambda(const rr_problem* p);
  * block 64*(i/256) + i%64 under counter (block, 0, lo32(b), hi32(b)) and key
  * (lo32(seed), hi32(seed)).  M is computed for every draw; the accepted draws are
  *   mode = RR_MODE_THRESHOLD: those with M <= q_or_a (section 2.2, Appendix A part C);
+ *   mode = RR_MODE_CHI2_QUANTILE: those with M <= c_q, the q-quantile of chi^2_d for
+ *     q = q_or_a in (0, 1] (section 2.2: the threshold a_q taken from the chi-square
+ *     approximation of M; rr_diagnose reports the same c_q);
  *   mode = RR_MODE_QUANTILE:  k = ceil(q N (1 - 1e-12)) draws with the smallest M
  *     (section 2.2, acceptance probability q), q = q_or_a in (0, 1]; values within a
  *     relative 1e-10 of the k-th smallest are ordered by key.

@@ -6,7 +6,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-MODE_QUANTILE, MODE_THRESHOLD = 0, 1
+MODE_QUANTILE, MODE_THRESHOLD, MODE_CHI2_QUANTILE = 0, 1, 2
 PREC_SPLIT_BF16, PREC_FP32 = 0, 1
 X_FP64, X_FP32 = 0, 1
 METRIC_MAHALANOBIS, METRIC_DIAGONAL = 0, 1

@@ -54,6 +54,7 @@ struct PoolRec {
     uint64_t* out_key;
     double* out_m;
     uint64_t capacity;
+    double a;             // threshold modes: the pool's threshold
 };
 
 __global__ void batch_init_kernel(AcceptState* st, int nprob, uint32_t k) {
@@ -67,7 +68,7 @@ __global__ void batch_init_kernel(AcceptState* st, int nprob, uint32_t k) {
 
 // One workgroup per pool: T_hi / T_lo by radix select over the pool's N draws (quantile
 // mode), then outright acceptances and guard-band members.
-__global__ __launch_bounds__(1024) void batch_select_kernel(const PoolRec* recs, uint32_t N, int mode, double a) {
+__global__ __launch_bounds__(1024) void batch_select_kernel(const PoolRec* recs, uint32_t N, int mode) {
     __shared__ uint32_t hist[2][256];
     __shared__ uint32_t s_prefix[2], s_krem[2], s_fail, s_acc, s_band;
     const PoolRec& r = recs[blockIdx.x];
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(1024) void batch_select_kernel(const PoolRec* recs,
     __syncthreads();
     for (uint32_t i = tid; i < N; i += blockDim.x) {
         bool acc, band;
-        classify_one(r.hi[i], r.lo[i], mode, a, lo_cut, hi_cut, &acc, &band);
+        classify_one(r.hi[i], r.lo[i], mode, r.a, lo_cut, hi_cut, &acc, &band);
         if (acc) {
             const uint32_t p = atomicAdd(&s_acc, 1u);
             if (p < r.acc_cap) {
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(1024) void batch_select_kernel(const PoolRec* recs,
 // One workgroup per pool: final rule over the rechecked band, then the accepted keys sorted
 // in LDS and written with their M to the caller's outputs (when they fit: at most
 // kFinishSort keys and the caller's capacity; otherwise the host finishes the pool).
-__global__ __launch_bounds__(1024) void batch_finish_kernel(const PoolRec* recs, int mode, double a) {
+__global__ __launch_bounds__(1024) void batch_finish_kernel(const PoolRec* recs, int mode) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t sk[kFinishSort];
     __shared__ uint32_t si[kFinishSort];
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(1024) void batch_finish_kernel(const PoolRec* recs,
     const PoolRec& r = recs[blockIdx.x];
     AcceptState* st = r.st;
     if (st->overflow || st->guard_fail) return;   // uniform: written by an earlier kernel
-    band_accept_block(r.band_key, r.band_m, r.band_work, st, mode, a, r.acc_key, r.acc_m, nullptr, r.acc_cap, hist);
+    band_accept_block(r.band_key, r.band_m, r.band_work, st, mode, r.a, r.acc_key, r.acc_m, nullptr, r.acc_cap, hist);
     __syncthreads();
     if (threadIdx.x == 0) {
         // atomics keep these reads at the coherence point the band atomics updated
@@ -234,7 +235,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     if (nprob == 0) return RR_OK;
     const uint64_t N = num_draws;
     if (N == 0 || N > 0xFFFFFFFFull || key_begin + N < key_begin ||
-        (mode != RR_MODE_QUANTILE && mode != RR_MODE_THRESHOLD) ||
+        (mode != RR_MODE_QUANTILE && mode != RR_MODE_THRESHOLD && mode != RR_MODE_CHI2_QUANTILE) ||
         (precision != RR_PREC_SPLIT_BF16 && precision != RR_PREC_FP32) || nprob > (1 << 20)) {
         set_error("rr_draw_balance_batched: invalid argument");
         return RR_E_ARG;
@@ -264,10 +265,19 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             set_error("rr_draw_balance_batched: capacity below the accepted count");
             return RR_E_CAPACITY;
         }
+    } else if (mode == RR_MODE_CHI2_QUANTILE) {
+        if (!(q_or_a > 0.0 && q_or_a <= 1.0)) {
+            set_error("rr_draw_balance_batched: q must be in (0, 1]");
+            return RR_E_ARG;
+        }
     } else if (std::isnan(q_or_a)) {
         set_error("rr_draw_balance_batched: threshold is NaN");
         return RR_E_ARG;
     }
+    // chi-square mode: each pool's threshold c_q of chi^2_d, then threshold acceptance
+    const bool chi2 = mode == RR_MODE_CHI2_QUANTILE;
+    const double q_in = q_or_a;
+    if (chi2) mode = RR_MODE_THRESHOLD;
     hipStream_t st = (hipStream_t)stream;
     Problem& lead = P[0]->P;
     if (!lead.batch) lead.batch = new BatchState();
@@ -434,6 +444,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         q.out_key = d_keys[i];
         q.out_m = d_M[i];
         q.capacity = capacity;
+        q.a = chi2 ? chi2_quantile_of(q_in, (double)P[i]->P.d) : q_or_a;
         pr[i] = q;
     }
     // tables go up before the graph runs (plain copies, not graph nodes)
@@ -449,7 +460,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     sig.push_back((uint64_t)nprob);
     sig.push_back(key_begin);
     sig.push_back(N);
-    sig.push_back((uint64_t)mode);
+    sig.push_back((uint64_t)mode | (chi2 ? 0x100u : 0u));
     uint64_t qbits;
     std::memcpy(&qbits, &q_or_a, 8);
     sig.push_back(qbits);
@@ -519,7 +530,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         check(hipEventRecord(join, B.s_gen));
         check(hipStreamWaitEvent(B.s_main, join, 0));
         hipLaunchKernelGGL(batch_select_kernel, dim3((unsigned)nprob), dim3(1024), 0, B.s_main, d_pr, (uint32_t)N,
-                           mode, q_or_a);
+                           mode);
         check(hipGetLastError());
         ++kernels;
         // the groups' rechecks are independent: alternate them over the two streams
@@ -537,7 +548,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         }
         check(hipEventRecord(join2, B.s_gen));
         check(hipStreamWaitEvent(B.s_main, join2, 0));
-        hipLaunchKernelGGL(batch_finish_kernel, dim3((unsigned)nprob), dim3(1024), 0, B.s_main, d_pr, mode, q_or_a);
+        hipLaunchKernelGGL(batch_finish_kernel, dim3((unsigned)nprob), dim3(1024), 0, B.s_main, d_pr, mode);
         check(hipGetLastError());
         ++kernels;
         hipGraph_t graph = nullptr;
@@ -577,8 +588,9 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         if (a.overflow || a.guard_fail) {
             // guard band beyond the batched capacity: the single-pool pipeline decides this pool
             const double keep_ms = graph_ms;
-            rr_status s = draw_pipeline(P[i]->P, false, seeds[i], key_begin, N, mode, q_or_a, precision, d_keys[i],
-                                        d_M[i], nullptr, capacity, &h_counts[i], B.s_main, nullptr);
+            rr_status s = draw_pipeline(P[i]->P, false, seeds[i], key_begin, N, chi2 ? RR_MODE_CHI2_QUANTILE : mode,
+                                        chi2 ? q_in : q_or_a, precision, d_keys[i], d_M[i], nullptr, capacity,
+                                        &h_counts[i], B.s_main, nullptr);
             graph_ms = keep_ms;
             if (s != RR_OK) result = s;
             continue;

@@ -126,6 +126,9 @@ double mse_accept_of(double v, double sigma, double r2, double sc) {
 }
 
 }  // namespace
+
+double chi2_quantile_of(double q, double d) { return q >= 1.0 ? INFINITY : chi2_quantile(q, d); }
+
 }  // namespace rr
 
 using namespace rr;

@@ -182,6 +182,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
 hipError_t sort_accepted(const uint64_t* acc_key, const double* acc_m, const uint8_t* acc_flag, uint32_t n,
                          uint64_t* const sk[2], uint32_t* const si[2], uint64_t* out_key, double* out_m,
                          uint8_t* out_flag, hipStream_t st);
+double chi2_quantile_of(double q, double d);   // q-quantile of chi^2_d (inf for q = 1)
 void set_timing(double total_ms, double contract_ms, double gen_ms, int64_t launches, uint64_t band);
 }  // namespace rr
 

@@ -452,6 +452,15 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
                         double q_or_a, int prec, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
                         uint64_t capacity, uint64_t* h_count, hipStream_t st, const Tune* tune) {
     auto t_start = std::chrono::steady_clock::now();
+    if (mode == RR_MODE_CHI2_QUANTILE) {
+        // a fixed threshold from the chi-square approximation of M
+        if (!(q_or_a > 0.0 && q_or_a <= 1.0)) {
+            set_error("rr_draw: q must be in (0, 1]");
+            return RR_E_ARG;
+        }
+        q_or_a = chi2_quantile_of(q_or_a, (double)P.d);
+        mode = RR_MODE_THRESHOLD;
+    }
     if (N == 0 || !d_keys || !d_M || !h_count || (mode != RR_MODE_QUANTILE && mode != RR_MODE_THRESHOLD) ||
         (prec != RR_PREC_SPLIT_BF16 && prec != RR_PREC_FP32)) {
         set_error("rr_draw: invalid argument");

@@ -197,3 +197,18 @@ def test_autotuner_file(rr, tmp_path):
         assert len(u64(keys)) == 105
     finally:
         os.environ.pop("RR_TUNE_FILE", None)
+
+
+def test_batched_chi2_threshold(rr):
+    """Chi-square threshold mode in a batch: every pool gets the c_q of its own d."""
+    say("batched chi-square threshold mode")
+    shapes = [(80, 5), (300, 33), (1000, 60), (1500, 200)]
+    _, Ps, seeds = _problems(rr, shapes, seed0=1200)
+    N = 6000
+    out = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_CHI2_QUANTILE, 0.1, rr.PREC_SPLIT_BF16,
+                                     capacity=N)
+    for i, (keys, M) in enumerate(out):
+        want_k, want_M = _single(rr, Ps[i], seeds[i], N, rr.MODE_CHI2_QUANTILE, 0.1, rr.PREC_SPLIT_BF16)
+        np.testing.assert_array_equal(u64(keys), want_k)
+        np.testing.assert_array_equal(M.cpu().numpy(), want_M)
+        assert 0 < len(want_k) < N

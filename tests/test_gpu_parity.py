@@ -246,3 +246,22 @@ def test_exact_enumeration_unbalanced(rr, mode, qa):
         Mg, fl = M.cpu().numpy(), flags.cpu().numpy().astype(bool)
         np.testing.assert_allclose(Mg[fl], Macc[fl], rtol=1e-9)
         np.testing.assert_allclose(Mg[~fl], Macc[~fl], rtol=1e-4)
+
+
+def test_chi2_threshold_mode(rr):
+    """Acceptance at M <= c_q(d), the chi-square quantile (threshold from the approximation)."""
+    from oracle import diagnose
+    say("chi-square threshold mode")
+    X = inputs.gaussian_X(100, 10, 31)
+    P = rr.rr_prepare(dev(X), 40, 0.0)
+    q, N = 0.05, 20_000
+    a = diagnose.c_q(q, 10)
+    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32):
+        keys, M, flags = rr.rr_draw_balance(P, 5, 0, N, rr.MODE_CHI2_QUANTILE, q, prec)
+        acc, Macc, _ = pipeline.draw_balance(X, 40, 0.0, 5, 0, N, "threshold", a)
+        np.testing.assert_array_equal(u64(keys), acc)
+        np.testing.assert_allclose(M.cpu().numpy(), Macc, rtol=1e-9)
+    assert abs(len(acc) / N - q) < 0.01      # M is close to chi^2_d here
+    with pytest.raises(rr.RRError) as e:
+        rr.rr_draw_balance(P, 5, 0, N, rr.MODE_CHI2_QUANTILE, 0.0, rr.PREC_SPLIT_BF16)
+    assert e.value.status == "RR_E_ARG"
