@@ -84,7 +84,7 @@ void contract_kernel(ContractArgs a0) {
         for (int e = tid; e < TILE * 8 * S; e += NW * 64) {
             const int dr = e / (8 * S), w = e % (8 * S);
             const uint64_t idx = tile0 + dr;
-            sbits[dr * WSTR + w] = idx < a.num ? a.bits[idx * (8 * S) + w] : 0u;
+            sbits[dr * WSTR + w] = idx < a.num ? __builtin_nontemporal_load(a.bits + idx * (8 * S) + w) : 0u;
         }
         issue_stage(0, 0);
         __builtin_amdgcn_s_waitcnt(0);

@@ -455,8 +455,11 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
             w[2 * r + 1] = (uint32_t)(bm >> 32);
         }
         if (lane == 0) {
-            reinterpret_cast<uint4*>(out + 8 * s)[0] = make_uint4(w[0], w[1], w[2], w[3]);
-            reinterpret_cast<uint4*>(out + 8 * s)[1] = make_uint4(w[4], w[5], w[6], w[7]);
+            // streaming stores: the bitmasks are read once, and should not push the contraction's
+            // operand records out of L2
+            typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store(u32x4{w[0], w[1], w[2], w[3]}, reinterpret_cast<u32x4*>(out + 8 * s));
+            __builtin_nontemporal_store(u32x4{w[4], w[5], w[6], w[7]}, reinterpret_cast<u32x4*>(out + 8 * s) + 1);
         }
     }
 }
