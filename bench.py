@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 METRIC = "balance-checked draws/sec at n=d=1000: BF16-split MFMA vs FP32, same accept set"
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 (matrix / vector)
+PEAK_INT8_TOPS = 5000.0        # MI355X dense int8 MFMA
 
 
 CONTRACT_SRC = os.path.join(ROOT, "paper_2501_07642_amd", "csrc", "rr_contract.hip")
@@ -100,6 +101,19 @@ def run_batched(args, rr, inputs, np, torch):
     ms_per_step = 1000.0 * (time.perf_counter() - t0) / args.steps
     kernels = rr.rr_last_timing()["launches"]
     band_total = rr.rr_last_timing()["band"]
+    i8 = None
+    if not args.no_i8:
+        rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_QUANTILE, q, rr.PREC_FIXED_I8)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            out8 = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_QUANTILE, q, rr.PREC_FIXED_I8)
+        torch.cuda.synchronize()
+        ms8 = 1000.0 * (time.perf_counter() - t1) / args.steps
+        same8 = all(bool(torch.equal(out8[i][0], out[i][0])) for i in range(len(Ps)))
+        i8 = {"draws_per_s": w["num_problems"] * N / (ms8 / 1000.0), "ms_per_step": ms8,
+              "graph_gpu_ms": rr.rr_last_timing()["contract_ms"], "same_accept_sets": same8,
+              "speedup_vs_split": ms_per_step / ms8}
     # per-pool launch sequences, one pass
     t1 = time.perf_counter()
     same = True
@@ -123,7 +137,7 @@ def run_batched(args, rr, inputs, np, torch):
         "mfma_tflops_over_graph": achieved, "frac_bf16_peak_over_graph": achieved / PEAK_BF16_TFLOPS,
         "per_pool_calls": {"ms": loop_ms, "draws_per_s": total / (loop_ms / 1000.0),
                            "batched_speedup": loop_ms / ms_per_step, "same_results_sampled": same},
-        "prepare_s_all_pools": prep_s}), flush=True)
+        "prepare_s_all_pools": prep_s, "i8_form": i8}), flush=True)
 
 
 def main():
@@ -136,6 +150,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=200000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-i8", action="store_true", help="skip the fixed-point int8 comparison leg")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (PMC byte-counter scale)")
     args = ap.parse_args()
@@ -167,10 +182,9 @@ def main():
     Xd = torch.from_numpy(X).to(dev)
     taus = w["taus"]
 
-    def step(Yd, obs):
+    def step(Yd, obs, prec=rr.PREC_SPLIT_BF16):
         P = rr.rr_prepare(Xd, n1, w["ridge_rel"])
-        keys, M, flags = rr.rr_draw_balance(P, w["seed"], w["key_begin"], N, rr.MODE_QUANTILE, q,
-                                            rr.PREC_SPLIT_BF16)
+        keys, M, flags = rr.rr_draw_balance(P, w["seed"], w["key_begin"], N, rr.MODE_QUANTILE, q, prec)
         t = rr.rr_last_timing()
         counts = None
         if Yd is not None:
@@ -229,6 +243,28 @@ def main():
                 "mfma_tflops": a32, "frac_fp32_peak": a32 / PEAK_FP32_TFLOPS,
                 "split_speedup": (N / dt) and value / (N / dt)}
 
+    i8 = None
+    if not args.no_i8:
+        # the same step with the fixed-point int8 operand form (exact int32 accumulation)
+        step(Yd, obs, rr.PREC_FIXED_I8)
+        torch.cuda.synchronize()
+        c8 = g8 = 0.0
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            _, keys8, t, _ = step(Yd, obs, rr.PREC_FIXED_I8)
+            c8 += t["contract_ms"]
+            g8 += t["gen_ms"]
+        torch.cuda.synchronize()
+        ms8 = 1000.0 * (time.perf_counter() - t1) / args.steps
+        a8 = flops_per_draw * N * args.steps / (c8 / 1000.0) / 1e12
+        i8 = {"draws_per_s": N / (ms8 / 1000.0), "ms_per_step": ms8, "contract_kernel_ms_per_step": c8 / args.steps,
+              "gen_kernel_ms_per_step": g8 / args.steps,
+              "same_accept_set": bool(np.array_equal(keys8.cpu().numpy(), keys_split)),
+              "mfma_tops": a8, "frac_int8_peak": a8 / PEAK_INT8_TOPS, "guard_band": t["band"],
+              "speedup_vs_split": ms_per_step / ms8,
+              "kernel": "contract_kernel<fixed I8> (x = s (128 hi + lo), 32x32x32 int8 MFMA, exact int32)",
+              "algorithmic_ops_per_draw": flops_per_draw}
+
     base = None
     if not args.no_cpu_baseline:
         base = cpu_baseline(X, w, args.cpu_sample)
@@ -240,7 +276,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "n1": n1, "d": d, "num_draws": N, "q": q,
                    "accepted": int(len(keys_split)), "ridge_rel": w["ridge_rel"], "precision": "split_bf16",
                    "step": "rr_prepare + rr_draw_balance + rr_rand_test(201 nulls)"},
-        "roofline": roofline, "cpu_baseline": base, "fp32_form": fp32,
+        "roofline": roofline, "cpu_baseline": base, "fp32_form": fp32, "i8_form": i8,
         "contract_kernel_ms_per_step": contract_ms / args.steps, "guard_band": band,
         "rand_test_counts_min": int(counts.min().item()) if counts is not None else None,
     }

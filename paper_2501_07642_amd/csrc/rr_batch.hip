@@ -30,11 +30,12 @@
 namespace rr {
 
 constexpr int kFinishSort = 2048;              // accepted keys sorted in LDS per pool
-constexpr uint32_t kBatchBandCap = 1u << 14;   // guard-band entries per pool
+constexpr uint32_t kBatchBandCap = 1u << 14;   // guard-band entries per pool (d < n - 1)
 constexpr size_t kBitsBudget = size_t(1) << 30;   // bytes per bitmask round buffer
-// Recheck workgroups per pool: a pool's band (up to kBatchBandCap entries, large where M
-// hardly varies across draws, e.g. d >= n - 1 with a small ridge) is spread over this many
-// workgroups; workgroups past a small band exit at once.
+// Recheck workgroups per pool: a pool's band (up to kBatchBandCap entries; up to every draw
+// where d >= n - 1, since there M hardly varies across draws under a small ridge and most
+// draws sit within the error bound of the boundary) is spread over this many workgroups;
+// workgroups past a small band exit at once.
 constexpr int kBatchRecheckWgs = 32;
 
 // Per-pool record of the acceptance stages (device).
@@ -236,7 +237,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     const uint64_t N = num_draws;
     if (N == 0 || N > 0xFFFFFFFFull || key_begin + N < key_begin ||
         (mode != RR_MODE_QUANTILE && mode != RR_MODE_THRESHOLD && mode != RR_MODE_CHI2_QUANTILE) ||
-        (precision != RR_PREC_SPLIT_BF16 && precision != RR_PREC_FP32) || nprob > (1 << 20)) {
+        !valid_prec(precision) || nprob > (1 << 20)) {
         set_error("rr_draw_balance_batched: invalid argument");
         return RR_E_ARG;
     }
@@ -315,7 +316,16 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     for (Group& g : groups) g.bits_off *= C;
     const uint64_t R = (N + C - 1) / C;
     const uint32_t acc_cap = (uint32_t)(mode == RR_MODE_QUANTILE ? k : std::min<uint64_t>(capacity, N));
-    const uint32_t band_cap = (uint32_t)std::min<uint64_t>(N, kBatchBandCap);
+    // guard-band capacity per pool, packed back to back
+    std::vector<uint32_t> bcap((size_t)nprob);
+    std::vector<size_t> boff((size_t)nprob);
+    size_t band_total_cap = 0;
+    for (int64_t i = 0; i < nprob; ++i) {
+        const Problem& Q = P[i]->P;
+        bcap[i] = (uint32_t)std::min<uint64_t>(N, Q.d >= Q.n - 1 ? N : kBatchBandCap);
+        boff[i] = band_total_cap;
+        band_total_cap += bcap[i];
+    }
 
     // ---- workspace
     size_t off = 0;
@@ -328,7 +338,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     const size_t o_hi = take(4 * np * N), o_lo = take(4 * np * N), o_m = take(4 * np * N);
     const size_t o_bits0 = take(4 * words_per_draw * C), o_bits1 = take(4 * words_per_draw * C);
     const size_t o_ak = take(8 * np * acc_cap), o_am = take(8 * np * acc_cap);
-    const size_t o_bk = take(8 * np * band_cap), o_bm = take(8 * np * band_cap), o_bw = take(np * band_cap);
+    const size_t o_bk = take(8 * band_total_cap), o_bm = take(8 * band_total_cap), o_bw = take(band_total_cap);
     const size_t o_st = take(sizeof(AcceptState) * np);
     const size_t o_gt = take(sizeof(GenArgs) * np * R), o_ct = take(sizeof(ContractArgs) * np * R);
     const size_t o_rt = take(sizeof(RecheckArgs) * np), o_rta = take(sizeof(RecheckArgs) * np);
@@ -406,24 +416,24 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             }
             RecheckArgs ra{};
             ra.X64 = Q.X64;
-            ra.keys = d_bk + (size_t)i * band_cap;
+            ra.keys = d_bk + boff[i];
             ra.count = &d_st[i].band_count;
-            ra.cap = band_cap;
+            ra.cap = bcap[i];
             ra.seed = seeds[i];
             ra.n = (int)Q.n;
             ra.n1 = (int)Q.n1;
             ra.d = (int)Q.d;
             ra.scale = Q.scale;
-            ra.out = d_bm + (size_t)i * band_cap;
+            ra.out = d_bm + boff[i];
             rt[gpos[gi] + j] = ra;
             // small d: the draws accepted outright are recomputed in FP64 as well (cap 0 skips)
             RecheckArgs rf = ra;
             rf.keys = d_ak + (size_t)i * acc_cap;
             rf.count = &d_st[i].acc_count;
-            rf.cap = Q.d <= kRefineMaxD ? acc_cap : 0u;
+            rf.cap = refine_accepted(Q, precision) ? acc_cap : 0u;
             rf.out = d_am + (size_t)i * acc_cap;
             rta[gpos[gi] + j] = rf;
-            any_refine = any_refine || Q.d <= kRefineMaxD;
+            any_refine = any_refine || refine_accepted(Q, precision);
             rt_order.push_back(i);
         }
     }
@@ -436,10 +446,10 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         q.acc_key = d_ak + (size_t)i * acc_cap;
         q.acc_m = d_am + (size_t)i * acc_cap;
         q.acc_cap = acc_cap;
-        q.band_key = d_bk + (size_t)i * band_cap;
-        q.band_m = d_bm + (size_t)i * band_cap;
-        q.band_work = d_bw + (size_t)i * band_cap;
-        q.band_cap = band_cap;
+        q.band_key = d_bk + boff[i];
+        q.band_m = d_bm + boff[i];
+        q.band_work = d_bw + boff[i];
+        q.band_cap = bcap[i];
         q.st = d_st + i;
         q.out_key = d_keys[i];
         q.out_m = d_M[i];

@@ -15,14 +15,21 @@
 // registers and across the two lane halves; the error bound needs only ||G||.
 //
 //   split BF16: X~ = hi + lo, two 32x32x16 BF16 MFMA per K step into one FP32 accumulator;
-//   FP32:       32x32x2 FP32 MFMA; each K step starts from zero and is added on the VALU.
+//   FP32:       32x32x2 FP32 MFMA; each K step starts from zero and is added on the VALU;
+//   fixed I8:   X~ = s (128 hi + lo) per block of 32 covariates; the A operand holds the
+//               digits (-hi, lo) of 16 units, the B operand the bytes (-128, 1) of each
+//               treated unit, so one 32x32x32 int8 MFMA per K step sums 128 hi + lo exactly
+//               in int32; the chunk epilogue scales by s in FP32.
 #include <algorithm>
+#include <type_traits>
 
 #include "rr_internal.h"
 
 namespace rr {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 
 constexpr int kKStage = kKStepsPerStage;   // K steps per LDS stage
@@ -39,7 +46,21 @@ __device__ __forceinline__ uint4 expand_bf16(uint32_t x) {
     return r;
 }
 
+// 8 bits -> 8 unit byte pairs (-128, 1) = 0x0180 per treated unit, 0 otherwise, laid out
+// like expand_bf16.
+__device__ __forceinline__ uint4 expand_i8(uint32_t x) {
+    const uint32_t y = x | (x << 15);
+    uint4 r;
+    r.x = __umul24(y & 0x00010001u, 0x0180u);
+    r.y = __umul24(y & 0x00040004u, 0x0180u >> 2);
+    r.z = __umul24(y & 0x00100010u, 0x0180u >> 4);
+    r.w = __umul24(y & 0x00400040u, 0x0180u >> 6);
+    return r;
+}
+
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+constexpr int planes_for(int prec) { return prec == RR_PREC_FIXED_I8 ? 1 : 2; }
 
 template <int PREC, int NW, int CB, int DB, int S, bool BATCH>
 // 8-wave tiles: at most 168 registers per wave (two waves per SIMD, 336 of the 512 registers),
@@ -48,15 +69,21 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 8
 void contract_kernel(ContractArgs a0) {
     constexpr int TILE = NW * 32 * DB;
     constexpr int WSTR = 8 * S + 1;                       // +1: 32 draws hit 32 banks
-    constexpr int REC = kKStage * CB * 2;                 // 1 KB plane records per stage
+    constexpr int PL = planes_for(PREC);
+    constexpr int RECU4 = 64 * PL;                         // uint4 per operand record
+    constexpr int REC = kKStage * CB * PL;                 // 1 KB plane records per stage
     constexpr int STAGE_U4 = REC * 64;
     static_assert(REC % NW == 0, "each wave loads the same number of plane records");
     extern __shared__ uint4 smem4[];
-    uint4* sA = smem4;                                     // [2][kKStage][CB][2 planes][64 lanes]
+    uint4* sA = smem4;                                     // [2][kKStage][CB][PL planes][64 lanes]
     uint32_t* sbits = reinterpret_cast<uint32_t*>(smem4 + 2 * STAGE_U4);   // [TILE][WSTR]
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int h = lane >> 5, j = lane & 31;
+    // A single pool's contraction is the longer of the two co-resident kernels: its waves
+    // issue ahead of the generation waves sharing the SIMD.  (In the batched graph the raised
+    // priority measured slower, so batched launches keep the default.)
+    if constexpr (!BATCH) __builtin_amdgcn_s_setprio(3);
     // Batched launches walk the (problem, tile) list of all pools; the list is ordered
     // longest problem first, so the grid-stride assignment balances uneven problems.
     const uint64_t ntiles = BATCH ? (uint64_t)a0.nprob * a0.tpp : (a0.num + TILE - 1) / TILE;
@@ -74,9 +101,9 @@ void contract_kernel(ContractArgs a0) {
             const int chunk = gs / nst, kst = gs % nst;
 #pragma unroll
             for (int r = wave; r < REC; r += NW) {
-                const int kk = r / (CB * 2), cb = (r >> 1) % CB, p = r & 1;
+                const int kk = r / (CB * PL), cb = (r / PL) % CB, p = r % PL;
                 const int k = kst * kKStage + kk;
-                const uint4* src = a.op + ((size_t)k * a.ncb + chunk * CB + cb) * kRecordU4 + 64 * p + lane;
+                const uint4* src = a.op + ((size_t)k * a.ncb + chunk * CB + cb) * RECU4 + 64 * p + lane;
                 __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(sA + buf * STAGE_U4 + r * 64), 16, 0, 0);
             }
         };
@@ -93,7 +120,8 @@ void contract_kernel(ContractArgs a0) {
         float ss[DB];
 #pragma unroll
         for (int db = 0; db < DB; ++db) ss[db] = 0.f;
-        f32x16 acc[CB][DB];
+        using AccT = std::conditional_t<PREC == RR_PREC_FIXED_I8, i32x16, f32x16>;
+        AccT acc[CB][DB];
         const uint32_t* myb = sbits + (wave * 32 * DB + j) * WSTR;
 
         for (int gs = 0; gs < total; ++gs) {
@@ -104,7 +132,7 @@ void contract_kernel(ContractArgs a0) {
 #pragma unroll
                     for (int db = 0; db < DB; ++db)
 #pragma unroll
-                        for (int e = 0; e < 16; ++e) acc[cb][db][e] = 0.f;
+                        for (int e = 0; e < 16; ++e) acc[cb][db][e] = 0;
             }
             if (gs + 1 < total) issue_stage(gs + 1, (gs + 1) & 1);
             const uint4* st = sA + (gs & 1) * STAGE_U4;
@@ -142,6 +170,36 @@ void contract_kernel(ContractArgs a0) {
                             acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[cb][p], Bc[db], acc[cb][db], 0, 0, 0);
                         __builtin_amdgcn_sched_barrier(0);
                         if (more && g < DB) Bn[g] = expand(kk + 1, g);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (more) {
+#pragma unroll
+                        for (int db = 0; db < DB; ++db) Bc[db] = Bn[db];
+                    }
+                }
+            } else if constexpr (PREC == RR_PREC_FIXED_I8) {
+                // As the split form with one plane: per K step one int8 MFMA per block pair.
+                auto expand = [&](int kk, int db) {
+                    const uint32_t w = wd[db][kk >> 1];
+                    return __builtin_bit_cast(i32x4, expand_i8((w >> (16 * (kk & 1) + 8 * h)) & 0xFFu));
+                };
+                i32x4 Bc[DB], Bn[DB];
+#pragma unroll
+                for (int db = 0; db < DB; ++db) Bc[db] = expand(0, db);
+#pragma unroll
+                for (int kk = 0; kk < kKStage; ++kk) {
+                    const bool more = kk + 1 < kKStage;
+                    i32x4 A[CB];
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) A[cb] = __builtin_bit_cast(i32x4, st[(kk * CB + cb) * 64 + lane]);
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int db = 0; db < DB; ++db)
+                            acc[cb][db] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[cb], Bc[db], acc[cb][db], 0, 0, 0);
+                        __builtin_amdgcn_sched_barrier(0);
+                        if (more && cb < DB) Bn[cb] = expand(kk + 1, cb);
                     }
                     __builtin_amdgcn_sched_barrier(0);
                     if (more) {
@@ -187,9 +245,22 @@ void contract_kernel(ContractArgs a0) {
                 for (int db = 0; db < DB; ++db) {
                     float s2 = 0.f;
 #pragma unroll
-                    for (int cb = 0; cb < CB; ++cb)
+                    for (int cb = 0; cb < CB; ++cb) {
+                        if constexpr (PREC == RR_PREC_FIXED_I8) {
+                            // G = s I, I the exact int32 sums of this block
+                            float t = 0.f;
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) s2 = fmaf(acc[cb][db][r], acc[cb][db][r], s2);
+                            for (int r = 0; r < 16; ++r) {
+                                const float g = (float)acc[cb][db][r];
+                                t = fmaf(g, g, t);
+                            }
+                            const float sc = a.bscale[chunk * CB + cb];
+                            s2 = fmaf(sc * sc, t, s2);
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < 16; ++r) s2 = fmaf(acc[cb][db][r], acc[cb][db][r], s2);
+                        }
+                    }
                     ss[db] += s2;
                 }
             }
@@ -246,18 +317,20 @@ void contract_kernel(ContractArgs a0) {
 // Tile shapes: covariate blocks per chunk (CB) and 32-draw blocks per wave (DB).  Split
 // BF16: 8 waves (two per SIMD, so one wave's bit expansion on the VALU overlaps the other's
 // MFMA), each with 2 x DB accumulator blocks of 32x32 (<= 168 registers, leaving room for
-// three generation waves per SIMD); FP32: 4 waves of 2 x DB blocks plus a per-K-step block
-// set.  The default DB is 2 where the tile's bitmasks fit in LDS beside the operand stages;
+// three generation waves per SIMD); fixed I8: the same shape with one operand plane (half
+// the LDS stage); FP32: 4 waves of 2 x DB blocks plus a per-K-step block set.  The default DB is 2 where the tile's bitmasks fit in LDS beside the operand stages;
 // the autotuner may pick 1.  Per-draw arithmetic (and so every M32) does not depend on NW
 // or DB, only on CB.
 constexpr int kCB = 2;
-constexpr int nw_for(int prec, int S) { return prec == RR_PREC_SPLIT_BF16 && S <= 8 ? 8 : 4; }
+constexpr bool mfma16(int prec) { return prec == RR_PREC_SPLIT_BF16 || prec == RR_PREC_FIXED_I8; }
+constexpr int nw_for(int prec, int S) { return mfma16(prec) && S <= 8 ? 8 : 4; }
 constexpr size_t lds_for(int prec, int S, int db) {
-    return sizeof(uint4) * 2 * kKStage * kCB * kRecordU4 + sizeof(uint32_t) * (nw_for(prec, S) * 32 * db) * (8 * S + 1);
+    return sizeof(uint4) * 2 * kKStage * kCB * 64 * planes_for(prec) +
+           sizeof(uint32_t) * (nw_for(prec, S) * 32 * db) * (8 * S + 1);
 }
 constexpr size_t kMaxLds = 160 * 1024;
 constexpr int db_default(int prec, int S) {
-    return prec == RR_PREC_SPLIT_BF16 ? (S <= 4 ? 2 : 1) : (S <= 8 ? 2 : 1);
+    return mfma16(prec) ? (S <= 4 ? 2 : 1) : (S <= 8 ? 2 : 1);
 }
 
 template <int PREC, int S, int DB, bool BATCH>
@@ -304,6 +377,9 @@ hipError_t launch_contract(int S, int prec, int db, bool batch, const ContractAr
     if (prec == RR_PREC_SPLIT_BF16)
         return batch ? launch_contract_p<RR_PREC_SPLIT_BF16, true>(S, db, a, grid, st)
                      : launch_contract_p<RR_PREC_SPLIT_BF16, false>(S, db, a, grid, st);
+    if (prec == RR_PREC_FIXED_I8)
+        return batch ? launch_contract_p<RR_PREC_FIXED_I8, true>(S, db, a, grid, st)
+                     : launch_contract_p<RR_PREC_FIXED_I8, false>(S, db, a, grid, st);
     return batch ? launch_contract_p<RR_PREC_FP32, true>(S, db, a, grid, st)
                  : launch_contract_p<RR_PREC_FP32, false>(S, db, a, grid, st);
 }
@@ -340,6 +416,8 @@ int contract_kernel_vgprs(int prec, int S, int db, bool batch) {
     if (!contract_db_ok(prec, S, db)) return 0;
     if (prec == RR_PREC_SPLIT_BF16)
         return batch ? contract_vgprs_p<RR_PREC_SPLIT_BF16, true>(S, db) : contract_vgprs_p<RR_PREC_SPLIT_BF16, false>(S, db);
+    if (prec == RR_PREC_FIXED_I8)
+        return batch ? contract_vgprs_p<RR_PREC_FIXED_I8, true>(S, db) : contract_vgprs_p<RR_PREC_FIXED_I8, false>(S, db);
     return batch ? contract_vgprs_p<RR_PREC_FP32, true>(S, db) : contract_vgprs_p<RR_PREC_FP32, false>(S, db);
 }
 int contract_waves(int prec, int S) { return nw_for(prec, S); }

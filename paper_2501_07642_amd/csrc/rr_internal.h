@@ -33,6 +33,11 @@ constexpr int kKStep = 16;            // units per MFMA K step (32x32x16 BF16)
 constexpr int kKStepsPerStage = 8;    // K steps per LDS stage of the contraction
 constexpr int kColBlock = 32;         // covariates per MFMA row block
 constexpr int kRecordU4 = 128;        // uint4 per operand record: 2 planes x 64 lanes x 16 B
+constexpr int kRecordU4I8 = 64;       // fixed-point int8 records: 1 plane x 64 lanes x 16 B
+// Fixed-point digits: x = s (128 hi + lo), hi in [-127, 127], lo in [-64, 63], so the
+// quantised value q = 128 hi + lo spans [-16320, 16319] and s = max|x| / kQMax per block.
+constexpr int kQMax = 16319;
+constexpr int kQMin = -16320;
 constexpr int kMaxS = RR_MAX_N / kUnitsPerChunk;   // 16
 
 // Host-side description of a prepared problem.
@@ -52,6 +57,9 @@ struct Problem {
     double* mu = nullptr;      // d column means
     uint4* op_split = nullptr; // ks * ncb records: BF16 hi / lo planes
     uint4* op_f32 = nullptr;   // ks * ncb records: FP32 planes
+    uint4* op_i8 = nullptr;    // ks * ncb records: fixed-point int8 digits (one plane)
+    float* bscale = nullptr;   // ncb fixed-point scales s, one per block of 32 covariates
+    double qerr_c2 = 0;        // sum_j e_j^2, e_j bounding the fixed-point error of G_j (host)
     float* cabs = nullptr;     // 32 * ncb column sums of |X~| (rounded up; 0 for pads)
     double cabs_c2 = 0;        // sum of cabs^2 (host copy, for the error bound)
     // workspace for the draw pipeline (grown on demand)
@@ -81,6 +89,7 @@ struct ContractArgs {
     const uint64_t* keylist;
     const uint4* op;          // operand records, ks * ncb records of kRecordU4 uint4
     const float* cabs;        // 32 * ncb
+    const float* bscale;      // fixed-point form: scale of each block of 32 covariates
     int n, ks, ncb;
     float scale;              // n / (n1 n0)
     float two_kappa;          // 2 * kappa: |G32_j - G_j| <= kappa * cabs_j
@@ -120,6 +129,15 @@ struct RecheckArgs {
 // hi + lo representation error of X~ (2^-18 relative per entry) makes the FP32 value's
 // relative error about 2^-17 sqrt(d / M), which can pass 1e-4 only at small d and tiny M.
 constexpr int kRefineMaxD = 64;
+
+inline bool valid_prec(int prec) {
+    return prec == RR_PREC_SPLIT_BF16 || prec == RR_PREC_FP32 || prec == RR_PREC_FIXED_I8;
+}
+// Accepted draws reported with their FP64 M: small d (see above) and the fixed-point form,
+// whose 15-bit representation of X~ leaves the FP32 value about 2^-13 sqrt(d / M) relative.
+inline bool refine_accepted(const Problem& P, int prec) {
+    return P.d <= kRefineMaxD || prec == RR_PREC_FIXED_I8;
+}
 
 // Launch configuration of the draw pipeline, chosen by the autotuner per problem bucket:
 // draws per wave block of the contraction tile (db, 1 or 2) and generation workgroups per CU.

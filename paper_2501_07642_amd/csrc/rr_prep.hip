@@ -206,6 +206,78 @@ __global__ void operands_kernel(const double* X, int64_t n, int64_t d, int64_t k
     }
 }
 
+// Fixed-point form.  Block cb of 32 covariates gets the scale s = max |X~| / kQMax over its
+// entries (rounded up to float, 1 for an all-zero block), so every entry quantises to
+// q = rint(x / s) in [kQMin, kQMax]; q = 128 hi + lo with hi = floor((q + 64) / 128).
+__global__ void block_scale_kernel(const double* X, int64_t n, int64_t d, float* bscale) {
+    __shared__ double red[256];
+    const int64_t cb = blockIdx.x;
+    double m = 0.0;
+    for (int64_t e = threadIdx.x; e < n * 32; e += blockDim.x) {
+        const int64_t i = e / 32, col = 32 * cb + e % 32;
+        if (col < d) m = fmax(m, fabs(X[i * d + col]));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double s = red[0] / (double)kQMax;
+        float f = (float)s;
+        if ((double)f < s) f = nextafterf(f, INFINITY);
+        bscale[cb] = red[0] > 0.0 ? f : 1.0f;
+    }
+}
+
+__device__ __forceinline__ int quantise(double x, float s) {
+    const double q = fmin(fmax(rint(x / (double)s), (double)kQMin), (double)kQMax);
+    return (int)q;
+}
+
+// Record (k, cb) of the fixed-point form: lane l = c + 32h holds, for t = 0..7, the digits of
+// unit u = 16k + 8h + t and covariate 32cb + c in bytes 2t (-hi) and 2t + 1 (lo).  The
+// contraction pairs them with the bytes -128 and 1 of a treated unit (0 otherwise), so one
+// int8 MFMA K step of 32 sums 16 units' 128 hi + lo exactly.
+__global__ void operands_i8_kernel(const double* X, int64_t n, int64_t d, int64_t ncb, const float* bscale,
+                                   uint4* op_i8) {
+    const int64_t rec = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t k = rec / ncb, cb = rec % ncb;
+    const int c = lane & 31, h = lane >> 5;
+    const int64_t col = 32 * cb + c;
+    const float s = bscale[cb];
+    uint32_t w[4];
+    for (int t2 = 0; t2 < 4; ++t2) {
+        uint32_t v = 0;
+        for (int q2 = 0; q2 < 2; ++q2) {
+            const int64_t unit = 16 * k + 8 * h + 2 * t2 + q2;
+            const int q = (unit < n && col < d) ? quantise(X[unit * d + col], s) : 0;
+            const int hi = (q + 64) >> 7;   // floor division (arithmetic shift)
+            const int lo = q - 128 * hi;
+            v |= (((uint32_t)(uint8_t)(int8_t)(-hi)) | ((uint32_t)(uint8_t)(int8_t)lo << 8)) << (16 * q2);
+        }
+        w[t2] = v;
+    }
+    op_i8[rec * kRecordU4I8 + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// e_j = max(sum of the positive, sum of the negative parts of s q_ij - x_ij) over all units
+// bounds |sum_{i in T} (s q_ij - x_ij)| for every treated set T; FP64, widened by 1e-12.
+__global__ void qerr_kernel(const double* X, int64_t n, int64_t d, const float* bscale, double* e) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= d) return;
+    const float s = bscale[j / 32];
+    double pos = 0.0, neg = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double x = X[i * d + j];
+        const double r = (double)s * (double)quantise(x, s) - x;
+        if (r > 0) pos += r; else neg -= r;
+    }
+    e[j] = fmax(pos, neg) * (1.0 + 1e-12);
+}
+
 // cabs_j = sum_i |X~_ij| rounded up to float; 0 for padded columns.
 __global__ void cabs_kernel(const double* X, int64_t n, int64_t d, int64_t dpad, float* cabs) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -262,9 +334,10 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     P.scale = (double)n / ((double)n1 * (double)(n - n1));
     const int64_t dpad = 32 * P.ncb;
 
-    double *S = nullptr, *piv = nullptr, *scal = nullptr;
+    double *S = nullptr, *piv = nullptr, *scal = nullptr, *qe = nullptr;
     int* bad = nullptr;
     auto fail = [&](rr_status s) {
+        hipFree(qe);
         hipFree(S);
         hipFree(piv);
         hipFree(scal);
@@ -286,6 +359,9 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     RR_PHIP(hipMalloc(&P.op_split, sizeof(uint4) * kRecordU4 * P.ks * P.ncb));
     RR_PHIP(hipMalloc(&P.op_f32, sizeof(uint4) * kRecordU4 * P.ks * P.ncb));
     RR_PHIP(hipMalloc(&P.cabs, sizeof(float) * dpad));
+    RR_PHIP(hipMalloc(&P.op_i8, sizeof(uint4) * kRecordU4I8 * P.ks * P.ncb));
+    RR_PHIP(hipMalloc(&P.bscale, sizeof(float) * P.ncb));
+    RR_PHIP(hipMalloc(&qe, sizeof(double) * d));
     RR_PHIP(hipMalloc(&piv, sizeof(double) * d));
     RR_PHIP(hipMalloc(&scal, sizeof(double) * 2));
     RR_PHIP(hipMalloc(&bad, sizeof(int)));
@@ -345,14 +421,27 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     hipLaunchKernelGGL(cabs_kernel, dim3((unsigned)((dpad + 255) / 256)), dim3(256), 0, st, P.X64, n, d, dpad,
                        P.cabs);
     RR_PHIP(hipGetLastError());
+    hipLaunchKernelGGL(block_scale_kernel, dim3((unsigned)P.ncb), dim3(256), 0, st, P.X64, n, d, P.bscale);
+    RR_PHIP(hipGetLastError());
+    hipLaunchKernelGGL(operands_i8_kernel, dim3((unsigned)(P.ks * P.ncb)), dim3(64), 0, st, P.X64, n, d, P.ncb,
+                       P.bscale, P.op_i8);
+    RR_PHIP(hipGetLastError());
+    hipLaunchKernelGGL(qerr_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, P.X64, n, d, P.bscale, qe);
+    RR_PHIP(hipGetLastError());
     {
         std::vector<float> hc((size_t)dpad);
+        std::vector<double> he((size_t)d);
         RR_PHIP(hipMemcpyAsync(hc.data(), P.cabs, sizeof(float) * dpad, hipMemcpyDeviceToHost, st));
+        RR_PHIP(hipMemcpyAsync(he.data(), qe, sizeof(double) * d, hipMemcpyDeviceToHost, st));
         RR_PHIP(hipStreamSynchronize(st));
         double c2 = 0.0;
         for (float c : hc) c2 += (double)c * (double)c;
         P.cabs_c2 = c2;
+        double e2 = 0.0;
+        for (double e : he) e2 += e * e;
+        P.qerr_c2 = e2 * (1.0 + 1e-12);
     }
+    hipFree(qe);
     hipFree(S);
     hipFree(piv);
     hipFree(scal);

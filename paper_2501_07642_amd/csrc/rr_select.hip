@@ -381,6 +381,20 @@ static double gamma_m(double m) { return m * kU / (1.0 - m * kU); }
 
 Bound bound_constants(const Problem& P, int prec) {
     const double ks = (double)P.ks;
+    if (prec == RR_PREC_FIXED_I8) {
+        // G32 is s q summed exactly; only the representation error (e_j, from the
+        // preparation) and the FP32 squares / scalings / sums (depth below) remain.
+        const int cb = draw_cb(prec, P.S);
+        const int chunks = (int)((P.ncb + cb - 1) / cb);
+        const double depth = 16.0 * cb + 2.0 * chunks + 8.0;
+        Bound b;
+        b.two_kappa = (float)(2.0 * (1.0 + gamma_m(depth)) * (1.0 + 1e-6));
+        b.csq = (float)(P.qerr_c2 * 1.01);
+        b.cnorm = (float)(std::sqrt(P.qerr_c2) * (1.0 + 1e-6));
+        b.gamma_ss = (float)(gamma_m(depth) * 1.01);
+        b.safety = 1.0f;   // no MFMA rounding model involved: the int32 sums are exact
+        return b;
+    }
     double kappa;
     if (prec == RR_PREC_SPLIT_BF16)
         kappa = (gamma_m(4.0 * ks) + gamma_m(7.0)) * (1.0 + 0x1p-8 + 0x1p-16) + 1.05 * 0x1p-18;
@@ -410,8 +424,9 @@ int device_cus(int dev) {
 
 ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b) {
     ContractArgs a{};
-    a.op = prec == RR_PREC_SPLIT_BF16 ? P.op_split : P.op_f32;
+    a.op = prec == RR_PREC_SPLIT_BF16 ? P.op_split : (prec == RR_PREC_FIXED_I8 ? P.op_i8 : P.op_f32);
     a.cabs = P.cabs;
+    a.bscale = P.bscale;
     a.n = (int)P.n;
     a.ks = (int)P.ks;
     a.ncb = (int)P.ncb;
@@ -462,7 +477,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         mode = RR_MODE_THRESHOLD;
     }
     if (N == 0 || !d_keys || !d_M || !h_count || (mode != RR_MODE_QUANTILE && mode != RR_MODE_THRESHOLD) ||
-        (prec != RR_PREC_SPLIT_BF16 && prec != RR_PREC_FP32)) {
+        !valid_prec(prec)) {
         set_error("rr_draw: invalid argument");
         return RR_E_ARG;
     }
@@ -608,7 +623,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
     ra.scale = P.scale;
     ra.out = w.band_m;
     RR_HIP(launch_recheck(P.S, exact, ra, (int)std::min<uint64_t>((hc.cand_count + 15) / 16 + 1, (uint64_t)device_cus(P.device) * 2), st));
-    if (P.d <= kRefineMaxD) {
+    if (refine_accepted(P, prec)) {
         // the draws accepted outright are reported with their FP64 values too
         RecheckArgs rf = ra;
         rf.keys = w.acc_key;
@@ -687,6 +702,8 @@ void rr_free(rr_problem* p) {
     hipFree(P.mu);
     hipFree(P.op_split);
     hipFree(P.op_f32);
+    hipFree(P.op_i8);
+    hipFree(P.bscale);
     hipFree(P.cabs);
     hipFree(P.ws);
     for (hipEvent_t e : P.events) hipEventDestroy(e);
@@ -753,7 +770,7 @@ rr_status rr_regenerate(rr_problem* p, uint64_t seed, int exact, const uint64_t*
 
 rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys, uint64_t K,
                           int precision, float* d_M32, float* d_err, double* d_M64, void* stream) {
-    if (!p || (K && !d_keys) || (precision != RR_PREC_SPLIT_BF16 && precision != RR_PREC_FP32) ||
+    if (!p || (K && !d_keys) || !valid_prec(precision) ||
         (!d_M32) != (!d_err) || K > 0xFFFFFFFFull) {
         set_error("rr_balance_keys: invalid argument");
         return RR_E_ARG;

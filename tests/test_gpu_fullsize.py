@@ -2,11 +2,11 @@
 on samples the oracle computes one by one and on properties that hold at any size.
 
   precision_n1000_d1000: 2e5 draws, AR(1) + Student-t covariates, q = 0.01 (2000 kept),
-      both operand forms: identical accepted sets; oracle M of every accepted draw and of
+      all three operand forms: identical accepted sets; oracle M of every accepted draw and of
       3000 sampled rejected draws: accepted max <= rejected min; M within 1e-9 (rechecked)
       or 1e-4 (FP32) relative; randomization-test counts equal the oracle's exactly.
   stream_n1000_d1000: 1e8 draws, q = 1.2e-5 (1200 kept), streaming prefilter: the same
-      sampled checks, and the FP32 form accepts the same set.
+      sampled checks, and the FP32 and fixed-point int8 forms accept the same set.
 """
 
 import sys
@@ -75,9 +75,13 @@ def test_precision_pool_both_forms_and_frt(rr):
     P = rr.rr_prepare(dev(X), w["n1"], w["ridge_rel"])
     ks, Ms, fs = rr.rr_draw_balance(P, w["seed"], 0, w["num_draws"], rr.MODE_QUANTILE, w["q"], rr.PREC_SPLIT_BF16)
     k32, M32, f32 = rr.rr_draw_balance(P, w["seed"], 0, w["num_draws"], rr.MODE_QUANTILE, w["q"], rr.PREC_FP32)
+    k8, M8, f8 = rr.rr_draw_balance(P, w["seed"], 0, w["num_draws"], rr.MODE_QUANTILE, w["q"], rr.PREC_FIXED_I8)
     np.testing.assert_array_equal(u64(ks), u64(k32))
+    np.testing.assert_array_equal(u64(ks), u64(k8))
     acc = _sampled_checks(X, w, ks, Ms, fs, np.random.default_rng(31))
     _sampled_checks(X, w, k32, M32, f32, np.random.default_rng(32), n_rej=500)
+    assert f8.cpu().numpy().all()
+    _sampled_checks(X, w, k8, M8, f8, np.random.default_rng(33), n_rej=500)
     # randomization test on the accepted pool
     obs = inputs.obs_pick(len(acc), w["obs_seed"])
     wo = pipeline.regenerate(w["seed"], acc[obs:obs + 1], w["n"], w["n1"])[0]
@@ -102,3 +106,9 @@ def test_stream_pool_sampled(rr):
     k32, _, _ = rr.rr_draw_balance(P, w["seed"], 0, w["num_draws"], rr.MODE_QUANTILE, w["q"], rr.PREC_FP32)
     say(f"  fp32: {rr.rr_last_timing()['total_ms']:.1f} ms")
     np.testing.assert_array_equal(u64(ks), u64(k32))
+    k8, M8, f8 = rr.rr_draw_balance(P, w["seed"], 0, w["num_draws"], rr.MODE_QUANTILE, w["q"], rr.PREC_FIXED_I8)
+    t = rr.rr_last_timing()
+    say(f"  fixed i8: {t['total_ms']:.1f} ms, band {t['band']}")
+    np.testing.assert_array_equal(u64(ks), u64(k8))
+    np.testing.assert_allclose(M8.cpu().numpy(), Ms.cpu().numpy(), rtol=1e-4)
+    assert f8.cpu().numpy().all()

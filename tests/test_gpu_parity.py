@@ -40,6 +40,10 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
 
 
+PRECS = {"split": lambda rr: rr.PREC_SPLIT_BF16, "fp32": lambda rr: rr.PREC_FP32,
+         "i8": lambda rr: rr.PREC_FIXED_I8}
+
+
 def u64(t):
     return t.cpu().numpy().astype(np.uint64)
 
@@ -77,28 +81,32 @@ def test_regenerate_exact_ranks(rr):
 
 @pytest.mark.parametrize("n,n1,d,ridge", [(20, 10, 3, 0.0), (60, 25, 8, 0.0), (100, 50, 100, 1e-2),
                                           (300, 150, 40, 0.0), (1000, 500, 1000, 1e-2)])
-@pytest.mark.parametrize("prec", ["split", "fp32"])
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8"])
 def test_balance_values_and_bound(rr, n, n1, d, ridge, prec):
     say(f"balance n={n} d={d} prec={prec}")
     X = inputs.gaussian_X(n, d, 3)
     P = rr.rr_prepare(dev(X), n1, ridge)
     seed = 99
     keys = np.arange(5000, 5000 + 256, dtype=np.uint64)
-    pr = rr.PREC_SPLIT_BF16 if prec == "split" else rr.PREC_FP32
+    pr = PRECS[prec](rr)
     m32, err, m64 = rr.rr_balance_keys(P, seed, keys_t(keys), pr)
     m32, err, m64 = m32.cpu().numpy(), err.cpu().numpy(), m64.cpu().numpy()
     Pr = prep.prepare(X, n1, ridge)
     W = assign.mc_assignments_batch(seed, keys, n, n1)
     want = balance.mahalanobis_batch(X, W, Pr["S_lam"])
     np.testing.assert_allclose(m64, want, rtol=1e-9)
-    np.testing.assert_allclose(m32, want, rtol=1e-4, atol=1e-4 * d * 1e-3)
+    if prec == "i8":
+        # 15-bit fixed point: about 2^-13 sqrt(d / M) relative (the bound below is the contract)
+        np.testing.assert_allclose(m32, want, rtol=5e-4 * np.sqrt(d / np.minimum(want, d)).max(), atol=1e-6 * d)
+    else:
+        np.testing.assert_allclose(m32, want, rtol=1e-4, atol=1e-4 * d * 1e-3)
     assert np.all(np.abs(m32.astype(np.float64) - m64) <= err)
     say(f"  max |m32-m64|/err = {np.max(np.abs(m32 - m64) / err):.3e}, err/M = {np.median(err / m64):.2e}")
 
 
 def _check_pool(rr, X, n1, ridge, seed, N, mode, qa, prec):
     P = rr.rr_prepare(dev(X), n1, ridge)
-    pr = rr.PREC_SPLIT_BF16 if prec == "split" else rr.PREC_FP32
+    pr = PRECS[prec](rr)
     md = rr.MODE_QUANTILE if mode == "quantile" else rr.MODE_THRESHOLD
     keys, M, flags = rr.rr_draw_balance(P, seed, 0, N, md, qa, pr)
     acc, Macc, Mall = pipeline.draw_balance(X, n1, ridge, seed, 0, N, mode, qa)
@@ -107,10 +115,12 @@ def _check_pool(rr, X, n1, ridge, seed, N, mode, qa, prec):
     Mg, fl = M.cpu().numpy(), flags.cpu().numpy().astype(bool)
     np.testing.assert_allclose(Mg[fl], Macc[fl], rtol=1e-9)
     np.testing.assert_allclose(Mg[~fl], Macc[~fl], rtol=1e-4)
+    if prec == "i8":
+        assert fl.all()   # the fixed-point form reports FP64 M for every accepted draw
     return P, got, rr.rr_last_timing()
 
 
-@pytest.mark.parametrize("prec", ["split", "fp32"])
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8"])
 @pytest.mark.parametrize("mode,qa", [("quantile", 0.05), ("quantile", 1e-3), ("threshold", 4.0)])
 def test_pool_small(rr, prec, mode, qa):
     say(f"pool small {mode} {qa} {prec}")
@@ -124,7 +134,8 @@ def test_pool_ragged_tiles(rr):
     for n, d, N in [(37, 5, 1), (37, 5, 63), (101, 33, 129), (531, 70, 1000)]:
         say(f"pool ragged n={n} d={d} N={N}")
         X = inputs.gaussian_X(n, d, n)
-        _check_pool(rr, X, n // 3, 1e-3, 7, N, "quantile", 0.1, "split")
+        for prec in ("split", "i8"):
+            _check_pool(rr, X, n // 3, 1e-3, 7, N, "quantile", 0.1, prec)
 
 
 def test_exact_enumeration_c1(rr):
@@ -132,7 +143,7 @@ def test_exact_enumeration_c1(rr):
     say("exact enumeration n=20")
     X = inputs.workload_X("exact_n20_d3")
     P = rr.rr_prepare(dev(X), w["n1"], 0.0)
-    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32):
+    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32, rr.PREC_FIXED_I8):
         keys, M, flags = rr.rr_draw_exact(P, rr.MODE_QUANTILE, w["q"], prec)
         acc, Macc, _ = pipeline.draw_exact(X, w["n1"], 0.0, "quantile", w["q"])
         assert len(acc) == 1848
@@ -199,13 +210,13 @@ def test_errors(rr):
     assert e.value.status == "RR_E_ARG"
 
 
-@pytest.mark.parametrize("prec", ["split", "fp32"])
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8"])
 def test_diagonal_metric_pool(rr, prec):
     """Standardise-only metric: same kernels on the column-scaled covariates."""
     say(f"diagonal metric pool {prec}")
     rng = np.random.default_rng(77)
     X = rng.standard_normal((300, 40)) @ rng.standard_normal((40, 40)) * rng.uniform(0.1, 10.0, 40)
-    pr = rr.PREC_SPLIT_BF16 if prec == "split" else rr.PREC_FP32
+    pr = PRECS[prec](rr)
     P = rr.rr_prepare(dev(X), 120, 1e-3, metric=rr.METRIC_DIAGONAL)
     keys, M, flags = rr.rr_draw_balance(P, 99, 0, 20_000, rr.MODE_QUANTILE, 0.01, pr)
     acc, Macc, Mall = pipeline.draw_balance(X, 120, 1e-3, 99, 0, 20_000, "quantile", 0.01, metric="diagonal")
@@ -228,7 +239,7 @@ def test_pool_large_n(rr, n, d, N):
     """n above 2048: 16 chunks of 256 units, generated with a runtime chunk count."""
     say(f"pool large n={n} d={d} N={N}")
     X = inputs.gaussian_X(n, d, n + 3)
-    for prec in ("split", "fp32"):
+    for prec in ("split", "fp32", "i8"):
         _check_pool(rr, X, n // 2 - 7, 1e-3, 99, N, "quantile", 0.02, prec)
 
 
@@ -239,7 +250,7 @@ def test_exact_enumeration_unbalanced(rr, mode, qa):
     X = inputs.gaussian_X(22, 4, 2201)
     P = rr.rr_prepare(dev(X), 6, 0.0)
     md = rr.MODE_QUANTILE if mode == "quantile" else rr.MODE_THRESHOLD
-    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32):
+    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32, rr.PREC_FIXED_I8):
         keys, M, flags = rr.rr_draw_exact(P, md, qa, prec)
         acc, Macc, _ = pipeline.draw_exact(X, 6, 0.0, mode, qa)
         np.testing.assert_array_equal(u64(keys), acc)
@@ -256,7 +267,7 @@ def test_chi2_threshold_mode(rr):
     P = rr.rr_prepare(dev(X), 40, 0.0)
     q, N = 0.05, 20_000
     a = diagnose.c_q(q, 10)
-    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32):
+    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32, rr.PREC_FIXED_I8):
         keys, M, flags = rr.rr_draw_balance(P, 5, 0, N, rr.MODE_CHI2_QUANTILE, q, prec)
         acc, Macc, _ = pipeline.draw_balance(X, 40, 0.0, 5, 0, N, "threshold", a)
         np.testing.assert_array_equal(u64(keys), acc)
