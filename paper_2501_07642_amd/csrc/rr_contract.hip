@@ -34,20 +34,18 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 
 constexpr int kKStage = kKStepsPerStage;   // K steps per LDS stage
 
-__device__ __forceinline__ uint4 expand_bf16(uint32_t x) {
-    // 8 bits -> 8 BF16 values (1.0 = 0x3F80 or 0): bit 2k -> low half of dword k,
-    // bit 2k+1 -> high half.  y holds bit i at i and at i + 15.
-    const uint32_t y = x | (x << 15);
-    uint4 r;
-    r.x = __umul24(y & 0x00010001u, 0x3F80u);
-    r.y = __umul24(y & 0x00040004u, 0x3F80u >> 2);
-    r.z = __umul24(y & 0x00100010u, 0x3F80u >> 4);
-    r.w = __umul24(y & 0x00400040u, 0x3F80u >> 6);
-    return r;
+// Split form: W enters as 2.0 (BF16 0x4000, a single bit per half) so that a B dword is a
+// rotation and a mask of the bitmask word: the operand records pair units u and u + 16 in a
+// dword (both bits 16 apart), and with xr = the word rotated right by 4h, dword t of K step
+// parity p is rotr(xr, 8p + t + 18) & 0x40004000 (unit bits land on 14 and 30).  G comes
+// out as 2G exactly, and the sum of squares is scaled back by 1/4 (exact).
+template <int P, int T>
+__device__ __forceinline__ uint32_t wdword_split(uint32_t xr) {
+    return __builtin_amdgcn_alignbit(xr, xr, (8 * P + T + 18) & 31) & 0x40004000u;
 }
 
-// 8 bits -> 8 unit byte pairs (-128, 1) = 0x0180 per treated unit, 0 otherwise, laid out
-// like expand_bf16.
+// 8 bits -> 8 unit byte pairs (-128, 1) = 0x0180 per treated unit, 0 otherwise: bit 2t ->
+// low half of dword t, bit 2t + 1 -> high half.  y holds bit i at i and at i + 15.
 __device__ __forceinline__ uint4 expand_i8(uint32_t x) {
     const uint32_t y = x | (x << 15);
     uint4 r;
@@ -145,9 +143,23 @@ void contract_kernel(ContractArgs a0) {
             if constexpr (PREC == RR_PREC_SPLIT_BF16) {
                 // Software pipeline: the B fragments of step kk + 1 are expanded between the
                 // MFMA groups of step kk (scheduling fences keep that order).
+                uint32_t wr[DB][kKStage / 2];
+#pragma unroll
+                for (int db = 0; db < DB; ++db)
+#pragma unroll
+                    for (int q = 0; q < kKStage / 2; ++q)
+                        wr[db][q] = __builtin_amdgcn_alignbit(wd[db][q], wd[db][q], 4 * h);
                 auto expand = [&](int kk, int db) {
-                    const uint32_t w = wd[db][kk >> 1];
-                    return __builtin_bit_cast(bf16x8, expand_bf16((w >> (16 * (kk & 1) + 8 * h)) & 0xFFu));
+                    const uint32_t x = wr[db][kk >> 1];
+                    uint4 r;
+                    if (kk & 1) {
+                        r = make_uint4(wdword_split<1, 0>(x), wdword_split<1, 1>(x), wdword_split<1, 2>(x),
+                                       wdword_split<1, 3>(x));
+                    } else {
+                        r = make_uint4(wdword_split<0, 0>(x), wdword_split<0, 1>(x), wdword_split<0, 2>(x),
+                                       wdword_split<0, 3>(x));
+                    }
+                    return __builtin_bit_cast(bf16x8, r);
                 };
                 bf16x8 Bc[DB], Bn[DB];
 #pragma unroll
@@ -270,7 +282,8 @@ void contract_kernel(ContractArgs a0) {
 
 #pragma unroll
         for (int db = 0; db < DB; ++db) {
-            const float s2 = ss[db] + __shfl_xor(ss[db], 32, 64);
+            // the split form summed (2G)^2
+            const float s2 = (ss[db] + __shfl_xor(ss[db], 32, 64)) * (PREC == RR_PREC_SPLIT_BF16 ? 0.25f : 1.0f);
             // sum_j |G_j| cabs_j <= ||G|| ||cabs|| (Cauchy-Schwarz); cnorm = ||cabs|| (1 + 2^-20)
             const float s1 = sqrtf(s2) * (1.0f + 0x1p-20f) * a.cnorm;
             const uint64_t idx = tile0 + wave * 32 * DB + 32 * db + j;

@@ -171,7 +171,9 @@ __device__ __forceinline__ float bf16_to_float(uint16_t h) { return __uint_as_fl
 
 // Operand records.  Record (k, cb) (index k * ncb + cb) covers units 16k..16k+15 and
 // covariates 32cb..32cb+31 in 2 planes of 64 lanes x 16 bytes; lane l = c + 32h:
-//   split: plane 0 = BF16 hi, plane 1 = BF16 lo of X~(16k + 8h + e, 32cb + c), e = 0..7;
+//   split: plane 0 = BF16 hi, plane 1 = BF16 lo; dword t of lane l holds units
+//          u = 32 (k / 2) + 8 (k % 2) + 4h + t (low half) and u + 16 (high half), so that
+//          the contraction finds both bits of a dword 16 apart in a bitmask word;
 //   fp32:  plane p holds X~(16k + 8p + 2q + h, 32cb + c), q = 0..3.
 __global__ void operands_kernel(const double* X, int64_t n, int64_t d, int64_t ks, int64_t ncb,
                                 uint4* op_split, uint4* op_f32) {
@@ -187,7 +189,7 @@ __global__ void operands_kernel(const double* X, int64_t n, int64_t d, int64_t k
     for (int e = 0; e < 8; e += 2) {
         uint16_t hv[2], lv[2];
         for (int q = 0; q < 2; ++q) {
-            const double v = x(16 * k + 8 * h + e + q);
+            const double v = x(32 * (k >> 1) + 8 * (k & 1) + 4 * h + e / 2 + 16 * q);
             const uint16_t hb = bf16_rne((float)v);
             const double r = v - (double)bf16_to_float(hb);
             hv[q] = hb;
