@@ -106,30 +106,28 @@ __global__ void ridge_kernel(double* S, int64_t d, double ridge_rel, double* out
     }
 }
 
-// Unblocked Cholesky of the nb x nb diagonal block at (k0, k0); pivots recorded.
-__global__ void potrf_diag_kernel(double* A, int64_t d, int64_t k0, int nb, double* pivots, int* bad) {
+// Unblocked Cholesky of the nb x nb diagonal block at (k0, k0); pivots recorded.  One
+// thread per block entry: step p scales column p and updates T[r][c] (p < c <= r) once.
+__global__ __launch_bounds__(kNB * kNB) void potrf_diag_kernel(double* A, int64_t d, int64_t k0, int nb,
+                                                                double* pivots, int* bad) {
     __shared__ double T[kNB][kNB + 1];
-    const int tx = threadIdx.x;
-    for (int e = tx; e < nb * nb; e += blockDim.x) T[e / nb][e % nb] = A[(k0 + e / nb) * d + k0 + e % nb];
+    const int c = threadIdx.x % kNB, r = threadIdx.x / kNB;
+    if (r < nb && c < nb) T[r][c] = A[(k0 + r) * d + k0 + c];
     __syncthreads();
     for (int p = 0; p < nb; ++p) {
-        if (tx == 0) {
+        if (threadIdx.x == 0) {
             const double v = T[p][p];
             pivots[k0 + p] = v;
             if (!(v > 0.0)) *bad = 1;
             T[p][p] = v > 0.0 ? sqrt(v) : 1.0;
         }
         __syncthreads();
-        if (tx > p && tx < nb) T[tx][p] /= T[p][p];
+        if (c == p && r > p && r < nb) T[r][p] /= T[p][p];
         __syncthreads();
-        if (tx > p && tx < nb)
-            for (int c = p + 1; c <= tx; ++c) T[tx][c] -= T[tx][p] * T[c][p];
+        if (c > p && c <= r && r < nb) T[r][c] -= T[r][p] * T[c][p];
         __syncthreads();
     }
-    for (int e = tx; e < nb * nb; e += blockDim.x) {
-        const int r = e / nb, c = e % nb;
-        A[(k0 + r) * d + k0 + c] = c <= r ? T[r][c] : 0.0;
-    }
+    if (r < nb && c < nb) A[(k0 + r) * d + k0 + c] = c <= r ? T[r][c] : 0.0;
 }
 
 // Diagonal metric: the factor is diag(sqrt(S_jj + lambda)) (standardise, do not decorrelate).
@@ -143,22 +141,32 @@ __global__ void diag_factor_kernel(double* A, int64_t d, double* pivots, int* ba
 }
 
 // Rows r0..r0+rows-1 of the nb-column block at column k0 of Mtx (leading dim ldm) are
-// replaced by x with x L11^T = row, L11 the nb x nb lower block of L at (k0, k0).
-__global__ void trsm_rows_kernel(double* Mtx, int64_t ldm, int64_t r0, int64_t rows, int64_t col0,
-                                 const double* L, int64_t d, int64_t k0, int nb) {
+// replaced by x with x L11^T = row, L11 the nb x nb lower block of L at (k0, k0).  One thread
+// per row, the row held in registers (the loops unroll over the block size).
+__global__ __launch_bounds__(128) void trsm_rows_kernel(double* Mtx, int64_t ldm, int64_t r0, int64_t rows,
+                                                        int64_t col0, const double* L, int64_t d, int64_t k0,
+                                                        int nb) {
     __shared__ double T[kNB][kNB + 1];
     for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) T[e / nb][e % nb] = L[(k0 + e / nb) * d + k0 + e % nb];
     __syncthreads();
     const int64_t r = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= r0 + rows) return;
-    double x[kNB];
     double* row = Mtx + r * ldm + col0;
-    for (int p = 0; p < nb; ++p) {
-        double v = row[p];
-        for (int t = 0; t < p; ++t) v -= x[t] * T[p][t];
-        x[p] = v / T[p][p];
+    double x[kNB];
+#pragma unroll
+    for (int p = 0; p < kNB; ++p) x[p] = p < nb ? row[p] : 0.0;
+#pragma unroll
+    for (int p = 0; p < kNB; ++p) {
+        if (p < nb) {
+            double v = x[p];
+#pragma unroll
+            for (int t = 0; t < p; ++t) v -= x[t] * T[p][t];
+            x[p] = v / T[p][p];
+        }
     }
-    for (int p = 0; p < nb; ++p) row[p] = x[p];
+#pragma unroll
+    for (int p = 0; p < kNB; ++p)
+        if (p < nb) row[p] = x[p];
 }
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
@@ -383,7 +391,7 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     }
     for (int64_t k0 = 0; k0 < d && metric == RR_METRIC_MAHALANOBIS; k0 += kNB) {
         const int nb = (int)std::min<int64_t>(kNB, d - k0);
-        hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(kNB), 0, st, A, d, k0, nb, piv, bad);
+        hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(kNB * kNB), 0, st, A, d, k0, nb, piv, bad);
         RR_PHIP(hipGetLastError());
         const int64_t r0 = k0 + nb, rows = d - r0;
         if (rows > 0) {
@@ -409,13 +417,17 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
         return fail(RR_E_SINGULAR);
     }
     // upper triangle of L to zero (the factor is lower triangular)
-    // X~ = Xc L^-T by column blocks: X[:, J] -= X~[:, <J] L[J, <J]^T, then solve with L[J, J].
+    // X~ = Xc L^-T by column blocks, right-looking: solve block J with L[J, J], then
+    // X[:, >J] -= X~[:, J] L[>J, J]^T (wide updates of depth nb).
     for (int64_t j0 = 0; j0 < d; j0 += kNB) {
         const int nb = (int)std::min<int64_t>(kNB, d - j0);
-        if (j0 > 0) RR_PHIP(gemm_nt(st, n, nb, j0, -1.0, P.X64, d, 1, A + j0 * d, d, 1, 1.0, P.X64 + j0, d));
         hipLaunchKernelGGL(trsm_rows_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, P.X64, d, 0, n,
                            j0, A, d, j0, nb);
         RR_PHIP(hipGetLastError());
+        const int64_t rest = d - j0 - nb;
+        if (rest > 0)
+            RR_PHIP(gemm_nt(st, n, rest, nb, -1.0, P.X64 + j0, d, 1, A + (j0 + nb) * d + j0, d, 1, 1.0,
+                            P.X64 + j0 + nb, d));
     }
     hipLaunchKernelGGL(operands_kernel, dim3((unsigned)(P.ks * P.ncb)), dim3(64), 0, st, P.X64, n, d, P.ks, P.ncb,
                        P.op_split, P.op_f32);
