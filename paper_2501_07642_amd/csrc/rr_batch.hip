@@ -32,11 +32,11 @@ namespace rr {
 constexpr int kFinishSort = 2048;              // accepted keys sorted in LDS per pool
 constexpr uint32_t kBatchBandCap = 1u << 14;   // guard-band entries per pool (d < n - 1)
 constexpr size_t kBitsBudget = size_t(1) << 30;   // bytes per bitmask round buffer
-// Recheck workgroups per pool: a pool's band (up to kBatchBandCap entries; up to every draw
-// where d >= n - 1, since there M hardly varies across draws under a small ridge and most
-// draws sit within the error bound of the boundary) is spread over this many workgroups;
-// workgroups past a small band exit at once.
-constexpr int kBatchRecheckWgs = 32;
+// Recheck workgroups per CU: the bands of a bitmask class (up to kBatchBandCap entries per
+// pool; up to every draw where d >= n - 1, since there M hardly varies across draws under a
+// small ridge and most draws sit within the error bound of the boundary) form one flat list
+// of tiles that this many workgroups per CU stride over.
+constexpr int kBatchRecheckWgsPerCu = 2;
 
 // Per-pool record of the acceptance stages (device).
 struct PoolRec {
@@ -343,6 +343,8 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     const size_t o_gt = take(sizeof(GenArgs) * np * R), o_ct = take(sizeof(ContractArgs) * np * R);
     const size_t o_rt = take(sizeof(RecheckArgs) * np), o_rta = take(sizeof(RecheckArgs) * np);
     const size_t o_pr = take(sizeof(PoolRec) * np);
+    const size_t noff = np + groups.size();   // tile offsets: nprob_g + 1 per group
+    const size_t o_off = take(4 * 2 * noff);
     if (off > B.ws_bytes) {
         if (B.exec) hipGraphExecDestroy(B.exec);
         if (B.graph) hipGraphDestroy(B.graph);
@@ -371,6 +373,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     RecheckArgs* d_rt = (RecheckArgs*)(base + o_rt);
     RecheckArgs* d_rta = (RecheckArgs*)(base + o_rta);
     PoolRec* d_pr = (PoolRec*)(base + o_pr);
+    uint32_t* d_off = (uint32_t*)(base + o_off);
 
     // ---- tables: [round][group order] for generation / contraction; pool order elsewhere
     std::vector<GenArgs> gt(np * R);
@@ -547,13 +550,14 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         check(hipEventRecord(fork2, B.s_main));
         check(hipStreamWaitEvent(B.s_gen, fork2, 0));
         for (size_t gi = 0; gi < groups.size(); ++gi) {
-            check(launch_recheck_batch(groups[gi].S, d_rt + gpos[gi], (int)groups[gi].idx.size(), kBatchRecheckWgs,
-                                       (gi & 1) ? B.s_gen : B.s_main));
-            ++kernels;
+            const int rgrid = kBatchRecheckWgsPerCu * cus;
+            check(launch_recheck_batch(groups[gi].S, d_rt + gpos[gi], (int)groups[gi].idx.size(),
+                                       d_off + gpos[gi] + gi, rgrid, (gi & 1) ? B.s_gen : B.s_main));
+            kernels += 2;
             if (any_refine) {
                 check(launch_recheck_batch(groups[gi].S, d_rta + gpos[gi], (int)groups[gi].idx.size(),
-                                           kBatchRecheckWgs, (gi & 1) ? B.s_gen : B.s_main));
-                ++kernels;
+                                           d_off + noff + gpos[gi] + gi, rgrid, (gi & 1) ? B.s_gen : B.s_main));
+                kernels += 2;
             }
         }
         check(hipEventRecord(join2, B.s_gen));

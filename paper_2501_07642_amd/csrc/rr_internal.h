@@ -186,7 +186,7 @@ int gen_kernel_vgprs(int S, bool batch);
 int gen_wg_fit(int prec, int S, int db, bool batch);
 int draw_cb(int prec, int S);
 hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hipStream_t st);
-hipError_t launch_recheck_batch(int S, const RecheckArgs* tab, int nprob, int gx, hipStream_t st);
+hipError_t launch_recheck_batch(int S, const RecheckArgs* tab, int nprob, uint32_t* offs, int grid, hipStream_t st);
 int pow2_chunks(int n);
 int device_cus(int dev);
 const uint64_t* binom_table(int dev);

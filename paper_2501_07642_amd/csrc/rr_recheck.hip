@@ -16,33 +16,35 @@ namespace rr {
 // l % 16], result item r of lane l is G[draw 4r + l / 16][column l % 16]).  A workgroup tile
 // is 1 group, or 4 groups for long lists (the guard bands of problems with d >= n - 1): then
 // each X~ fragment loaded feeds four MFMAs and X~ is read once per 64 draws, at the cost of
-// more registers and fewer, longer tiles.  The four waves
-// regenerate the treated sets into LDS, then split the 16-column blocks; each wave adds G^2
-// of its blocks per draw and the partial sums are reduced in a fixed order (16 lanes, then
-// the four waves), so the value depends neither on the launch shape nor on the tile size.
-
+// more registers and fewer, longer tiles.  The NW = 4 waves of a workgroup regenerate the
+// treated sets into LDS, then split the 16-column blocks; each wave adds G^2 of its blocks
+// per draw and the partial sums are reduced in a fixed order (16 lanes, then the waves in
+// index order), so the value depends neither on the launch shape nor on the tile size.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 struct RecheckShared {
     uint32_t* bits;        // [16 G][8 S + 1]
-    uint2* list;           // [4][128]
-    double* red;           // [4][16 G]
+    uint2* list;           // [NW][128]
+    double* red;           // [NW][16 G]
 };
 
+constexpr int recheck_waves(int) { return 4; }
+
+// Entries e0 .. min(e0 + 16 G, cnt) - 1 of the list (workgroup-uniform arguments).
 template <int S, bool EXACT, int G>
-__device__ __forceinline__ void recheck_run(const RecheckArgs& a, uint32_t wg, uint32_t nwg, RecheckShared sh) {
+__device__ __forceinline__ void recheck_tile(const RecheckArgs& a, uint32_t e0, uint32_t cnt, RecheckShared sh) {
+    constexpr int NW = recheck_waves(S);
     constexpr int WS = 8 * S + 1;
     constexpr int kRecheckGroups = G;
     constexpr int kRecheckTile = 16 * G;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
-    const uint32_t cnt = min(*a.count, a.cap);
     const int ncolb = (a.d + 15) / 16;
     const int nk = (a.n + 31) / 32;                 // 32-unit words of a bitmask
     constexpr uint32_t tile = kRecheckTile;
-    for (uint32_t e0 = wg * tile; e0 < cnt; e0 += nwg * tile) {
+    {
         const int nt = (int)min<uint32_t>(tile, cnt - e0);
-        for (int t = wave; t < (int)tile; t += 4) {
+        for (int t = wave; t < (int)tile; t += NW) {
             uint32_t* bt = sh.bits + t * WS;
             if (t < nt) {
                 if constexpr (EXACT) {
@@ -61,18 +63,28 @@ __device__ __forceinline__ void recheck_run(const RecheckArgs& a, uint32_t wg, u
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
-        for (int e = tid; e < 4 * kRecheckTile; e += blockDim.x) sh.red[e] = 0.0;
+        for (int e = tid; e < NW * kRecheckTile; e += blockDim.x) sh.red[e] = 0.0;
         __syncthreads();
         // groups past the tile's draws skip their MFMAs (wave-uniform)
         const int ngroups = (nt + 15) / 16;
         double part[kRecheckGroups][4] = {};
-        for (int cbk = wave; cbk < ncolb; cbk += 4) {
-            const int col = 16 * cbk + c;
-            const bool cval = col < a.d;
-            const double* xcol = a.X64 + (cval ? col : 0);
-            f64x4 acc[kRecheckGroups];
+        // A wave takes its column blocks CBW at a time (blocks cb0 + j NW), so that each K
+        // step issues CBW independent X~ loads and CBW x G independent MFMA chains.
+        constexpr int CBW = 4;
+        for (int cb0 = wave; cb0 < ncolb; cb0 += NW * CBW) {
+            const double* xcol[CBW];
+            bool cval[CBW];
 #pragma unroll
-            for (int q = 0; q < kRecheckGroups; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+            for (int j = 0; j < CBW; ++j) {
+                const int col = 16 * (cb0 + j * NW) + c;
+                cval[j] = col < a.d;
+                xcol[j] = a.X64 + (cval[j] ? col : 0);
+            }
+            f64x4 acc[CBW][kRecheckGroups];
+#pragma unroll
+            for (int j = 0; j < CBW; ++j)
+#pragma unroll
+                for (int q = 0; q < kRecheckGroups; ++q) acc[j][q] = f64x4{0.0, 0.0, 0.0, 0.0};
             for (int kw = 0; kw < nk; ++kw) {
                 // 32 units = 8 K steps of 4; bitmask bits past n are zero
                 uint32_t word[kRecheckGroups];
@@ -81,20 +93,27 @@ __device__ __forceinline__ void recheck_run(const RecheckArgs& a, uint32_t wg, u
 #pragma unroll
                 for (int st = 0; st < 8; ++st) {
                     const int unit = 32 * kw + 4 * st + g;
-                    const double bv = (cval && unit < a.n) ? xcol[(size_t)unit * a.d] : 0.0;
+                    double bv[CBW];
+#pragma unroll
+                    for (int j = 0; j < CBW; ++j) bv[j] = (cval[j] && unit < a.n) ? xcol[j][(size_t)unit * a.d] : 0.0;
 #pragma unroll
                     for (int q = 0; q < kRecheckGroups; ++q) {
                         if (q < ngroups) {
                             const double av = ((word[q] >> (4 * st + g)) & 1u) ? 1.0 : 0.0;
-                            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+#pragma unroll
+                            for (int j = 0; j < CBW; ++j)
+                                acc[j][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[j], acc[j][q], 0, 0, 0);
                         }
                     }
                 }
             }
+            // blocks past ncolb hold zeros (their loads were masked)
 #pragma unroll
-            for (int q = 0; q < kRecheckGroups; ++q)
+            for (int j = 0; j < CBW; ++j)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) part[q][r] = fma(acc[q][r], acc[q][r], part[q][r]);
+                for (int q = 0; q < kRecheckGroups; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) part[q][r] = fma(acc[j][q][r], acc[j][q][r], part[q][r]);
         }
         // part[q][r] of lane (g, c): draw 16 q + 4 r + g, column c of this wave's blocks
 #pragma unroll
@@ -108,43 +127,86 @@ __device__ __forceinline__ void recheck_run(const RecheckArgs& a, uint32_t wg, u
             }
         __syncthreads();
         if (tid < nt) {
-            const double* rr = sh.red;
-            a.out[e0 + tid] = a.scale * ((rr[tid] + rr[kRecheckTile + tid]) + (rr[2 * kRecheckTile + tid] + rr[3 * kRecheckTile + tid]));
+            double v = sh.red[tid];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) v += sh.red[w * kRecheckTile + tid];
+            a.out[e0 + tid] = a.scale * v;
         }
         __syncthreads();
     }
 }
 
-template <int S, bool EXACT, int G>
-__device__ __forceinline__ void recheck_dispatch(const RecheckArgs& a, uint32_t wg, uint32_t nwg) {
-    __shared__ uint32_t bits[16 * G * (8 * S + 1)];
-    __shared__ uint2 list[4 * 128];
-    __shared__ double red[4 * 16 * G];
+#define RR_RECHECK_SHARED(S, G)                                  \
+    __shared__ uint32_t bits[16 * (G) * (8 * (S) + 1)];           \
+    __shared__ uint2 list[recheck_waves(S) * 128];               \
+    __shared__ double red[recheck_waves(S) * 16 * (G)];          \
     const RecheckShared sh{bits, list, red};
-    recheck_run<S, EXACT, G>(a, wg, nwg, sh);
-}
 
 template <int S, bool EXACT>
-__global__ __launch_bounds__(256) void recheck_kernel(RecheckArgs a) {
-    recheck_dispatch<S, EXACT, 1>(a, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(64 * recheck_waves(S)) void recheck_kernel(RecheckArgs a) {
+    RR_RECHECK_SHARED(S, 1)
+    const uint32_t cnt = min(*a.count, a.cap);
+    for (uint32_t e0 = blockIdx.x * 16u; e0 < cnt; e0 += gridDim.x * 16u) recheck_tile<S, EXACT, 1>(a, e0, cnt, sh);
 }
 
-// Batched: pool tab[blockIdx.y], its entries strided over blockIdx.x.
+// Batched: one flat list of the tiles of all pools of a bitmask class.  offs[p] is the
+// first tile of pool p (offs[nprob] the total), written by recheck_offsets_kernel from the
+// pools' list lengths; workgroups stride over the tiles, so every pool's band is spread over
+// the whole GPU whatever its length.
 template <int S, int G>
-__global__ __launch_bounds__(256) void recheck_batch_kernel(const RecheckArgs* tab) {
-    recheck_dispatch<S, false, G>(tab[blockIdx.y], blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(64 * recheck_waves(S)) void recheck_batch_kernel(const RecheckArgs* tab, int nprob,
+                                                                             const uint32_t* offs) {
+    RR_RECHECK_SHARED(S, G)
+    const uint32_t total = offs[nprob];
+    for (uint32_t T = blockIdx.x; T < total; T += gridDim.x) {
+        int lo = 0, hi = nprob;   // offs[lo] <= T < offs[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (offs[mid] <= T) lo = mid; else hi = mid;
+        }
+        const RecheckArgs& a = tab[lo];
+        const uint32_t cnt = min(*a.count, a.cap);
+        recheck_tile<S, false, G>(a, (T - offs[lo]) * (16u * G), cnt, sh);
+    }
+}
+#undef RR_RECHECK_SHARED
+
+// offs[p + 1] = offs[p] + ceil(len_p / tile), offs[0] = 0; one 1024-thread workgroup.
+__global__ __launch_bounds__(1024) void recheck_offsets_kernel(const RecheckArgs* tab, int nprob, uint32_t tile,
+                                                               uint32_t* offs) {
+    __shared__ uint32_t part[1024];
+    uint32_t base = 0;
+    for (int c0 = 0; c0 < nprob; c0 += 1024) {
+        const int i = c0 + (int)threadIdx.x;
+        uint32_t v = 0;
+        if (i < nprob) v = (min(*tab[i].count, tab[i].cap) + tile - 1) / tile;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const uint32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+            __syncthreads();
+            part[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nprob) offs[i + 1] = base + part[threadIdx.x];
+        base += part[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) offs[0] = 0;
 }
 
 // Pools of up to 512 units (S <= 2) include every problem with d >= n - 1 in the batched
 // workloads, whose bands are most of their draws: 64-draw tiles there, 16 elsewhere.
-hipError_t launch_recheck_batch(int S, const RecheckArgs* tab, int nprob, int gx, hipStream_t st) {
-    const dim3 grid((unsigned)std::max(1, gx), (unsigned)nprob);
+hipError_t launch_recheck_batch(int S, const RecheckArgs* tab, int nprob, uint32_t* offs, int grid, hipStream_t st) {
+    grid = std::max(1, grid);
+    const uint32_t tile = S <= 2 ? 64u : 16u;
+    hipLaunchKernelGGL(recheck_offsets_kernel, dim3(1), dim3(1024), 0, st, tab, nprob, tile, offs);
     switch (S) {
-        case 1: hipLaunchKernelGGL((recheck_batch_kernel<1, 4>), grid, dim3(256), 0, st, tab); break;
-        case 2: hipLaunchKernelGGL((recheck_batch_kernel<2, 4>), grid, dim3(256), 0, st, tab); break;
-        case 4: hipLaunchKernelGGL((recheck_batch_kernel<4, 1>), grid, dim3(256), 0, st, tab); break;
-        case 8: hipLaunchKernelGGL((recheck_batch_kernel<8, 1>), grid, dim3(256), 0, st, tab); break;
-        case 16: hipLaunchKernelGGL((recheck_batch_kernel<16, 1>), grid, dim3(256), 0, st, tab); break;
+        case 1: hipLaunchKernelGGL((recheck_batch_kernel<1, 4>), dim3(grid), dim3(64 * recheck_waves(1)), 0, st, tab, nprob, offs); break;
+        case 2: hipLaunchKernelGGL((recheck_batch_kernel<2, 4>), dim3(grid), dim3(64 * recheck_waves(2)), 0, st, tab, nprob, offs); break;
+        case 4: hipLaunchKernelGGL((recheck_batch_kernel<4, 1>), dim3(grid), dim3(64 * recheck_waves(4)), 0, st, tab, nprob, offs); break;
+        case 8: hipLaunchKernelGGL((recheck_batch_kernel<8, 1>), dim3(grid), dim3(64 * recheck_waves(8)), 0, st, tab, nprob, offs); break;
+        case 16: hipLaunchKernelGGL((recheck_batch_kernel<16, 1>), dim3(grid), dim3(64 * recheck_waves(16)), 0, st, tab, nprob, offs); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -153,14 +215,14 @@ hipError_t launch_recheck_batch(int S, const RecheckArgs* tab, int nprob, int gx
 hipError_t launch_recheck(int S, bool exact, const RecheckArgs& a, int grid, hipStream_t st) {
     grid = std::max(1, grid);
     if (exact) {
-        hipLaunchKernelGGL((recheck_kernel<1, true>), dim3(grid), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((recheck_kernel<1, true>), dim3(grid), dim3(64 * recheck_waves(1)), 0, st, a);
     } else {
         switch (S) {
-            case 1: hipLaunchKernelGGL((recheck_kernel<1, false>), dim3(grid), dim3(256), 0, st, a); break;
-            case 2: hipLaunchKernelGGL((recheck_kernel<2, false>), dim3(grid), dim3(256), 0, st, a); break;
-            case 4: hipLaunchKernelGGL((recheck_kernel<4, false>), dim3(grid), dim3(256), 0, st, a); break;
-            case 8: hipLaunchKernelGGL((recheck_kernel<8, false>), dim3(grid), dim3(256), 0, st, a); break;
-            case 16: hipLaunchKernelGGL((recheck_kernel<16, false>), dim3(grid), dim3(256), 0, st, a); break;
+            case 1: hipLaunchKernelGGL((recheck_kernel<1, false>), dim3(grid), dim3(64 * recheck_waves(1)), 0, st, a); break;
+            case 2: hipLaunchKernelGGL((recheck_kernel<2, false>), dim3(grid), dim3(64 * recheck_waves(2)), 0, st, a); break;
+            case 4: hipLaunchKernelGGL((recheck_kernel<4, false>), dim3(grid), dim3(64 * recheck_waves(4)), 0, st, a); break;
+            case 8: hipLaunchKernelGGL((recheck_kernel<8, false>), dim3(grid), dim3(64 * recheck_waves(8)), 0, st, a); break;
+            case 16: hipLaunchKernelGGL((recheck_kernel<16, false>), dim3(grid), dim3(64 * recheck_waves(16)), 0, st, a); break;
             default: return hipErrorInvalidValue;
         }
     }
