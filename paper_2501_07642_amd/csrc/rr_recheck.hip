@@ -171,28 +171,24 @@ __global__ __launch_bounds__(64 * recheck_waves(S)) void recheck_batch_kernel(co
 }
 #undef RR_RECHECK_SHARED
 
-// offs[p + 1] = offs[p] + ceil(len_p / tile), offs[0] = 0; one 1024-thread workgroup.
-__global__ __launch_bounds__(1024) void recheck_offsets_kernel(const RecheckArgs* tab, int nprob, uint32_t tile,
-                                                               uint32_t* offs) {
-    __shared__ uint32_t part[1024];
+// offs[p + 1] = offs[p] + ceil(len_p / tile), offs[0] = 0.  One wave (it must not wait for a
+// large slot while the other stream's rechecks hold the CUs), 64 pools per step.
+__global__ __launch_bounds__(64) void recheck_offsets_kernel(const RecheckArgs* tab, int nprob, uint32_t tile,
+                                                             uint32_t* offs) {
+    const int lane = threadIdx.x;
     uint32_t base = 0;
-    for (int c0 = 0; c0 < nprob; c0 += 1024) {
-        const int i = c0 + (int)threadIdx.x;
-        uint32_t v = 0;
-        if (i < nprob) v = (min(*tab[i].count, tab[i].cap) + tile - 1) / tile;
-        part[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            const uint32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
-            __syncthreads();
-            part[threadIdx.x] += t;
-            __syncthreads();
+    for (int c0 = 0; c0 < nprob; c0 += 64) {
+        const int i = c0 + lane;
+        uint32_t v = i < nprob ? (min(*tab[i].count, tab[i].cap) + tile - 1) / tile : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(v, o, 64);
+            if (lane >= o) v += t;
         }
-        if (i < nprob) offs[i + 1] = base + part[threadIdx.x];
-        base += part[1023];
-        __syncthreads();
+        if (i < nprob) offs[i + 1] = base + v;
+        base += __shfl(v, 63, 64);
     }
-    if (threadIdx.x == 0) offs[0] = 0;
+    if (lane == 0) offs[0] = 0;
 }
 
 // Pools of up to 512 units (S <= 2) include every problem with d >= n - 1 in the batched
@@ -200,7 +196,7 @@ __global__ __launch_bounds__(1024) void recheck_offsets_kernel(const RecheckArgs
 hipError_t launch_recheck_batch(int S, const RecheckArgs* tab, int nprob, uint32_t* offs, int grid, hipStream_t st) {
     grid = std::max(1, grid);
     const uint32_t tile = S <= 2 ? 64u : 16u;
-    hipLaunchKernelGGL(recheck_offsets_kernel, dim3(1), dim3(1024), 0, st, tab, nprob, tile, offs);
+    hipLaunchKernelGGL(recheck_offsets_kernel, dim3(1), dim3(64), 0, st, tab, nprob, tile, offs);
     switch (S) {
         case 1: hipLaunchKernelGGL((recheck_batch_kernel<1, 4>), dim3(grid), dim3(64 * recheck_waves(1)), 0, st, tab, nprob, offs); break;
         case 2: hipLaunchKernelGGL((recheck_batch_kernel<2, 4>), dim3(grid), dim3(64 * recheck_waves(2)), 0, st, tab, nprob, offs); break;
