@@ -93,10 +93,11 @@ def test_batched_threshold_and_ragged(rr):
     shapes = [(50, 10), (300, 33), (1000, 250), (2000, 20)]
     Xs, Ps, seeds = _problems(rr, shapes, seed0=950)
     N = 4_099
-    for a in (0.0, 8.0, 60.0):
-        out = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_THRESHOLD, a, rr.PREC_SPLIT_BF16, capacity=N)
+    for a, pr in ((0.0, rr.PREC_SPLIT_BF16), (8.0, rr.PREC_SPLIT_BF16), (60.0, rr.PREC_SPLIT_BF16),
+                  (8.0, rr.PREC_FIXED_I8)):
+        out = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_THRESHOLD, a, pr, capacity=N)
         for i, (keys, M) in enumerate(out):
-            want_k, want_M = _single(rr, Ps[i], seeds[i], N, rr.MODE_THRESHOLD, a, rr.PREC_SPLIT_BF16)
+            want_k, want_M = _single(rr, Ps[i], seeds[i], N, rr.MODE_THRESHOLD, a, pr)
             np.testing.assert_array_equal(u64(keys), want_k)
             np.testing.assert_array_equal(M.cpu().numpy(), want_M)
     acc, _, _ = pipeline.draw_balance(Xs[0].astype(np.float64), 25, 1e-2, seeds[0], 0, N, "threshold", 8.0)
