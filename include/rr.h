@@ -50,7 +50,7 @@ typedef enum {
 } rr_status;
 
 enum { RR_MODE_QUANTILE = 0, RR_MODE_THRESHOLD = 1, RR_MODE_CHI2_QUANTILE = 2 };
-enum { RR_PREC_SPLIT_BF16 = 0, RR_PREC_FP32 = 1, RR_PREC_FIXED_I8 = 2 };
+enum { RR_PREC_SPLIT_BF16 = 0, RR_PREC_FP32 = 1, RR_PREC_FIXED_I8 = 2, RR_PREC_GRAM_BF16 = 3 };
 enum { RR_X_FP64 = 0, RR_X_FP32 = 1 };
 enum { RR_METRIC_MAHALANOBIS = 0, RR_METRIC_DIAGONAL = 1 };
 
@@ -123,14 +123,16 @@ double rr_problem_lambda(const rr_problem* p);
  * precision selects the operand format of the W X~ contraction: RR_PREC_SPLIT_BF16
  * (X~ = hi + lo in BF16, FP32 accumulation), RR_PREC_FP32, or RR_PREC_FIXED_I8 (X~ in
  * 15-bit fixed point per block of 32 covariates, x = s (128 hi + lo) with int8 digits,
- * summed exactly in int32 on the int8 matrix cores).  Every draw whose FP32 value is not
- * provably on one side of the acceptance boundary is recomputed in FP64, so the accepted
- * set does not depend on the precision.
+ * summed exactly in int32 on the int8 matrix cores), or RR_PREC_GRAM_BF16 (the Gram form
+ * M = n/(n1 n0) w^T (X~ X~^T) w: the n x n Gram matrix split into BF16 hi + lo, n^2 instead
+ * of n d work per draw, for d > n; the Gram operands are built on the first call that asks
+ * for them).  Every draw whose FP32 value is not provably on one side of the acceptance
+ * boundary is recomputed in FP64, so the accepted set does not depend on the precision.
  *
  * Outputs (device, caller-allocated, `capacity` entries):
  *   d_keys   accepted keys, ascending;
  *   d_M      their M: the FP64 recomputation for draws of the guard band and, when d <= 64
- *            or precision = RR_PREC_FIXED_I8, for every accepted draw (the BF16 hi + lo
+ *            or precision = RR_PREC_FIXED_I8 or RR_PREC_GRAM_BF16, for every accepted draw (the BF16 hi + lo
  *            representation of X~ limits the FP32 value's relative accuracy to about
  *            2^-17 sqrt(d / M), the fixed-point one to about 2^-13 sqrt(d / M)); else the
  *            FP32 value, within 1e-4 relative;

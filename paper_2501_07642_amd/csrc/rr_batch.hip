@@ -289,6 +289,12 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     if (!B.t1) RR_HIP(hipEventCreate(&B.t1));
     if (!B.join) RR_HIP(hipEventCreateWithFlags(&B.join, hipEventDisableTiming));
     const int cus = device_cus(dev);
+    if (precision == RR_PREC_GRAM_BF16) {
+        for (int64_t i = 0; i < nprob; ++i) {
+            const rr_status s = ensure_gram(P[i]->P, st);
+            if (s != RR_OK) return s;
+        }
+    }
 
     // ---- plan: groups by S, largest work first; tiles per group from the autotuner
     std::vector<Group> groups;

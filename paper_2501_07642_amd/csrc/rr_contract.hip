@@ -16,6 +16,9 @@
 //
 //   split BF16: X~ = hi + lo, two 32x32x16 BF16 MFMA per K step into one FP32 accumulator;
 //   FP32:       32x32x2 FP32 MFMA; each K step starts from zero and is added on the VALU;
+//   Gram:       the split form with K = X~ X~^T (n x n) in place of X~: G'_j = sum_{i in T} K_ij
+//               for every unit j, and M = n / (n1 n0) sum_{j in T} G'_j (the epilogue reads
+//               the treated bits of its rows from the tile's bitmasks); n^2 instead of n d work;
 //   fixed I8:   X~ = s (128 hi + lo) per block of 32 covariates; the A operand holds the
 //               digits (-hi, lo) of 16 units, the B operand the bytes (-128, 1) of each
 //               treated unit, so one 32x32x32 int8 MFMA per K step sums 128 hi + lo exactly
@@ -67,6 +70,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 8
 void contract_kernel(ContractArgs a0) {
     constexpr int TILE = NW * 32 * DB;
     constexpr int WSTR = 8 * S + 1;                       // +1: 32 draws hit 32 banks
+    constexpr bool kGram = PREC == RR_PREC_GRAM_BF16;
+    constexpr bool kSplitLike = PREC == RR_PREC_SPLIT_BF16 || kGram;
     constexpr int PL = planes_for(PREC);
     constexpr int RECU4 = 64 * PL;                         // uint4 per operand record
     constexpr int REC = kKStage * CB * PL;                 // 1 KB plane records per stage
@@ -115,9 +120,9 @@ void contract_kernel(ContractArgs a0) {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
 
-        float ss[DB];
+        float ss[DB], ssa[DB];
 #pragma unroll
-        for (int db = 0; db < DB; ++db) ss[db] = 0.f;
+        for (int db = 0; db < DB; ++db) ss[db] = ssa[db] = 0.f;
         using AccT = std::conditional_t<PREC == RR_PREC_FIXED_I8, i32x16, f32x16>;
         AccT acc[CB][DB];
         const uint32_t* myb = sbits + (wave * 32 * DB + j) * WSTR;
@@ -140,7 +145,7 @@ void contract_kernel(ContractArgs a0) {
             for (int db = 0; db < DB; ++db)
 #pragma unroll
                 for (int q = 0; q < kKStage / 2; ++q) wd[db][q] = myb[32 * db * WSTR + (kKStage / 2) * kst + q];
-            if constexpr (PREC == RR_PREC_SPLIT_BF16) {
+            if constexpr (kSplitLike) {
                 // Software pipeline: the B fragments of step kk + 1 are expanded between the
                 // MFMA groups of step kk (scheduling fences keep that order).
                 uint32_t wr[DB][kKStage / 2];
@@ -255,10 +260,21 @@ void contract_kernel(ContractArgs a0) {
                 // ||G||^2 over this chunk's covariates
 #pragma unroll
                 for (int db = 0; db < DB; ++db) {
-                    float s2 = 0.f;
+                    float s2 = 0.f, sa = 0.f;
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb) {
-                        if constexpr (PREC == RR_PREC_FIXED_I8) {
+                        if constexpr (kGram) {
+                            // rows 8 (r / 4) + 4h + r % 4 of unit block chunk CB + cb: one
+                            // bitmask word of this lane's draw
+                            const uint32_t wb = myb[32 * db * WSTR + chunk * CB + cb];
+#pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                const bool t = (wb >> (8 * (r / 4) + 4 * h + (r % 4))) & 1u;
+                                const float v = acc[cb][db][r];
+                                s2 += t ? v : 0.f;
+                                sa += t ? fabsf(v) : 0.f;
+                            }
+                        } else if constexpr (PREC == RR_PREC_FIXED_I8) {
                             // G = s I, I the exact int32 sums of this block
                             float t = 0.f;
 #pragma unroll
@@ -274,6 +290,7 @@ void contract_kernel(ContractArgs a0) {
                         }
                     }
                     ss[db] += s2;
+                    if constexpr (kGram) ssa[db] += sa;
                 }
             }
             __builtin_amdgcn_s_waitcnt(0);     // this wave's loads of the next stage landed
@@ -282,14 +299,23 @@ void contract_kernel(ContractArgs a0) {
 
 #pragma unroll
         for (int db = 0; db < DB; ++db) {
-            // the split form summed (2G)^2
-            const float s2 = (ss[db] + __shfl_xor(ss[db], 32, 64)) * (PREC == RR_PREC_SPLIT_BF16 ? 0.25f : 1.0f);
-            // sum_j |G_j| cabs_j <= ||G|| ||cabs|| (Cauchy-Schwarz); cnorm = ||cabs|| (1 + 2^-20)
-            const float s1 = sqrtf(s2) * (1.0f + 0x1p-20f) * a.cnorm;
+            // the split form summed (2G)^2, the Gram form 2 G' (W enters as 2.0)
+            const float s2 = (ss[db] + __shfl_xor(ss[db], 32, 64)) *
+                             (PREC == RR_PREC_SPLIT_BF16 ? 0.25f : (kGram ? 0.5f : 1.0f));
             const uint64_t idx = tile0 + wave * 32 * DB + 32 * db + j;
             const bool live = h == 0 && idx < a.num;
-            const float m32 = a.scale * s2;
-            const float err = a.safety * (a.scale * (a.two_kappa * s1 + a.csq) + a.gamma_ss * m32);
+            float m32, err;
+            if constexpr (kGram) {
+                // M >= 0: clamping a rounded negative sum keeps the bound and the key order
+                const float sa = (ssa[db] + __shfl_xor(ssa[db], 32, 64)) * 0.5f;
+                m32 = fmaxf(a.scale * s2, 0.0f);
+                err = a.safety * (a.scale * (a.csq + a.gamma_ss * sa));
+            } else {
+                // sum_j |G_j| cabs_j <= ||G|| ||cabs|| (Cauchy-Schwarz); cnorm = ||cabs|| (1 + 2^-20)
+                const float s1 = sqrtf(s2) * (1.0f + 0x1p-20f) * a.cnorm;
+                m32 = a.scale * s2;
+                err = a.safety * (a.scale * (a.two_kappa * s1 + a.csq) + a.gamma_ss * m32);
+            }
             const float hi = (m32 + err) * (1.0f + 0x1p-21f);
             const float lo = fmaxf((m32 - err) * (1.0f - 0x1p-21f), 0.0f);
             if (a.out_err) {
@@ -335,7 +361,9 @@ void contract_kernel(ContractArgs a0) {
 // the autotuner may pick 1.  Per-draw arithmetic (and so every M32) does not depend on NW
 // or DB, only on CB.
 constexpr int kCB = 2;
-constexpr bool mfma16(int prec) { return prec == RR_PREC_SPLIT_BF16 || prec == RR_PREC_FIXED_I8; }
+constexpr bool mfma16(int prec) {
+    return prec == RR_PREC_SPLIT_BF16 || prec == RR_PREC_FIXED_I8 || prec == RR_PREC_GRAM_BF16;
+}
 constexpr int nw_for(int prec, int S) { return mfma16(prec) && S <= 8 ? 8 : 4; }
 constexpr size_t lds_for(int prec, int S, int db) {
     return sizeof(uint4) * 2 * kKStage * kCB * 64 * planes_for(prec) +
@@ -393,6 +421,9 @@ hipError_t launch_contract(int S, int prec, int db, bool batch, const ContractAr
     if (prec == RR_PREC_FIXED_I8)
         return batch ? launch_contract_p<RR_PREC_FIXED_I8, true>(S, db, a, grid, st)
                      : launch_contract_p<RR_PREC_FIXED_I8, false>(S, db, a, grid, st);
+    if (prec == RR_PREC_GRAM_BF16)
+        return batch ? launch_contract_p<RR_PREC_GRAM_BF16, true>(S, db, a, grid, st)
+                     : launch_contract_p<RR_PREC_GRAM_BF16, false>(S, db, a, grid, st);
     return batch ? launch_contract_p<RR_PREC_FP32, true>(S, db, a, grid, st)
                  : launch_contract_p<RR_PREC_FP32, false>(S, db, a, grid, st);
 }
@@ -431,6 +462,8 @@ int contract_kernel_vgprs(int prec, int S, int db, bool batch) {
         return batch ? contract_vgprs_p<RR_PREC_SPLIT_BF16, true>(S, db) : contract_vgprs_p<RR_PREC_SPLIT_BF16, false>(S, db);
     if (prec == RR_PREC_FIXED_I8)
         return batch ? contract_vgprs_p<RR_PREC_FIXED_I8, true>(S, db) : contract_vgprs_p<RR_PREC_FIXED_I8, false>(S, db);
+    if (prec == RR_PREC_GRAM_BF16)
+        return batch ? contract_vgprs_p<RR_PREC_GRAM_BF16, true>(S, db) : contract_vgprs_p<RR_PREC_GRAM_BF16, false>(S, db);
     return batch ? contract_vgprs_p<RR_PREC_FP32, true>(S, db) : contract_vgprs_p<RR_PREC_FP32, false>(S, db);
 }
 int contract_waves(int prec, int S) { return nw_for(prec, S); }

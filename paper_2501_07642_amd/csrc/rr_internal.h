@@ -60,6 +60,11 @@ struct Problem {
     uint4* op_i8 = nullptr;    // ks * ncb records: fixed-point int8 digits (one plane)
     float* bscale = nullptr;   // ncb fixed-point scales s, one per block of 32 covariates
     double qerr_c2 = 0;        // sum_j e_j^2, e_j bounding the fixed-point error of G_j (host)
+    // Gram form (built on first use): records of K = X~ X~^T in the split layout, its units
+    // taking the place of the covariates
+    uint4* op_gram = nullptr;  // ks * ncb_gram records: BF16 hi / lo planes of K
+    int64_t ncb_gram = 0;      // blocks of 32 units (padded to whole chunks)
+    double gram_ctop = 0;      // sum of the n1 largest column sums of |K| (host, error bound)
     float* cabs = nullptr;     // 32 * ncb column sums of |X~| (rounded up; 0 for pads)
     double cabs_c2 = 0;        // sum of cabs^2 (host copy, for the error bound)
     // workspace for the draw pipeline (grown on demand)
@@ -131,13 +136,18 @@ struct RecheckArgs {
 constexpr int kRefineMaxD = 64;
 
 inline bool valid_prec(int prec) {
-    return prec == RR_PREC_SPLIT_BF16 || prec == RR_PREC_FP32 || prec == RR_PREC_FIXED_I8;
+    return prec == RR_PREC_SPLIT_BF16 || prec == RR_PREC_FP32 || prec == RR_PREC_FIXED_I8 ||
+           prec == RR_PREC_GRAM_BF16;
 }
-// Accepted draws reported with their FP64 M: small d (see above) and the fixed-point form,
-// whose 15-bit representation of X~ leaves the FP32 value about 2^-13 sqrt(d / M) relative.
+// Accepted draws reported with their FP64 M: small d (see above), the fixed-point form, whose
+// 15-bit representation of X~ leaves the FP32 value about 2^-13 sqrt(d / M) relative, and the
+// Gram form, whose sum w^T K w can cancel (its FP32 value has no relative bound).
 inline bool refine_accepted(const Problem& P, int prec) {
-    return P.d <= kRefineMaxD || prec == RR_PREC_FIXED_I8;
+    return P.d <= kRefineMaxD || prec == RR_PREC_FIXED_I8 || prec == RR_PREC_GRAM_BF16;
 }
+// Builds the Gram-form operands of a prepared problem if they are missing (stream-ordered,
+// synchronises the stream once).
+rr_status ensure_gram(Problem& P, hipStream_t st);
 
 // Launch configuration of the draw pipeline, chosen by the autotuner per problem bucket:
 // draws per wave block of the contraction tile (db, 1 or 2) and generation workgroups per CU.

@@ -10,8 +10,11 @@
 // blocked right-looking Cholesky (diagonal block in LDS, row solves for the panel, GEMM
 // update of the trailing matrix); X~ by blocked forward substitution; BF16 hi/lo and FP32
 // operand records for the W X~ contraction; column sums of |X~| for the error bound.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <vector>
 
 #include "rr_internal.h"
 
@@ -208,6 +211,7 @@ __global__ void operands_kernel(const double* X, int64_t n, int64_t d, int64_t k
     }
     op_split[rec * kRecordU4 + lane] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
     op_split[rec * kRecordU4 + 64 + lane] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    if (!op_f32) return;
     for (int p = 0; p < 2; ++p) {
         float f[4];
         for (int q = 0; q < 4; ++q) f[q] = (float)x(16 * k + 8 * p + 2 * q + h);
@@ -462,6 +466,50 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     hipFree(bad);
 #undef RR_PHIP
     *out = h;
+    return RR_OK;
+}
+
+// Gram form: K = X~ X~^T (n x n, FP64), its split operand records with K's columns in the
+// place of the covariates (K is symmetric), and the error-bound constant sum of the n1
+// largest column sums of |K|.
+rr_status ensure_gram(Problem& P, hipStream_t st) {
+    if (P.op_gram) return RR_OK;
+    const int64_t n = P.n, d = P.d;
+    const int64_t cbq = 2;
+    const int64_t ncb = cbq * ((n + 32 * cbq - 1) / (32 * cbq));
+    const int64_t npad = 32 * ncb;
+    double* K = nullptr;
+    float* cabs = nullptr;
+    uint4* op = nullptr;
+    auto fail = [&](hipError_t e) {
+        hipFree(K);
+        hipFree(cabs);
+        hipFree(op);
+        set_error(std::string("rr_draw: Gram operands: ") + hipGetErrorString(e));
+        return RR_E_DEVICE;
+    };
+    hipError_t e = hipMalloc(&K, sizeof(double) * n * n);
+    if (e == hipSuccess) e = hipMalloc(&cabs, sizeof(float) * npad);
+    if (e == hipSuccess) e = hipMalloc(&op, sizeof(uint4) * kRecordU4 * P.ks * ncb);
+    if (e != hipSuccess) return fail(e);
+    e = gemm_nt(st, n, n, d, 1.0, P.X64, d, 1, P.X64, d, 1, 0.0, K, n);
+    if (e != hipSuccess) return fail(e);
+    hipLaunchKernelGGL(operands_kernel, dim3((unsigned)(P.ks * ncb)), dim3(64), 0, st, K, n, n, P.ks, ncb, op,
+                       (uint4*)nullptr);
+    hipLaunchKernelGGL(cabs_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, st, K, n, n, npad, cabs);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+    std::vector<float> hc((size_t)npad);
+    if ((e = hipMemcpyAsync(hc.data(), cabs, sizeof(float) * npad, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return fail(e);
+    std::sort(hc.begin(), hc.end(), [](float x, float y) { return x > y; });
+    double top = 0.0;
+    for (int64_t i = 0; i < P.n1 && i < npad; ++i) top += (double)hc[i];
+    hipFree(K);
+    hipFree(cabs);
+    P.op_gram = op;
+    P.ncb_gram = ncb;
+    P.gram_ctop = top * (1.0 + 1e-12);
     return RR_OK;
 }
 

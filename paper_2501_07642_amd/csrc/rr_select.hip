@@ -396,10 +396,25 @@ Bound bound_constants(const Problem& P, int prec) {
         return b;
     }
     double kappa;
-    if (prec == RR_PREC_SPLIT_BF16)
+    if (prec == RR_PREC_SPLIT_BF16 || prec == RR_PREC_GRAM_BF16)
         kappa = (gamma_m(4.0 * ks) + gamma_m(7.0)) * (1.0 + 0x1p-8 + 0x1p-16) + 1.05 * 0x1p-18;
     else
         kappa = gamma_m(16.0 + ks) * (1.0 + 0x1p-23) + 0x1p-24;
+    if (prec == RR_PREC_GRAM_BF16) {
+        // G'_j = sum_{i in T} K_ij errs by at most kappa cabsK_j; M = scale sum_{j in T} G'_j, so
+        // |M32 - M| <= scale (kappa sum_{j in T} cabsK_j + gamma(depth) sum_{j in T} |G'32_j|),
+        // and sum_{j in T} cabsK_j <= the sum of the n1 largest column sums (gram_ctop).
+        const int cb = draw_cb(prec, P.S);
+        const int chunks = (int)((P.ncb_gram + cb - 1) / cb);
+        const double depth = 16.0 * cb + chunks + 6.0;
+        Bound b;
+        b.two_kappa = 0.0f;
+        b.cnorm = 0.0f;
+        b.csq = (float)(kappa * P.gram_ctop * 1.01);
+        b.gamma_ss = (float)(gamma_m(depth) * 1.01);
+        b.safety = (float)kSafety;
+        return b;
+    }
     const double c2 = P.cabs_c2;
     const int cb = draw_cb(prec, P.S);
     const int chunks = (int)((P.ncb + cb - 1) / cb);
@@ -424,12 +439,15 @@ int device_cus(int dev) {
 
 ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b) {
     ContractArgs a{};
-    a.op = prec == RR_PREC_SPLIT_BF16 ? P.op_split : (prec == RR_PREC_FIXED_I8 ? P.op_i8 : P.op_f32);
+    a.op = prec == RR_PREC_SPLIT_BF16 ? P.op_split
+         : prec == RR_PREC_FIXED_I8   ? P.op_i8
+         : prec == RR_PREC_GRAM_BF16  ? P.op_gram
+                                      : P.op_f32;
     a.cabs = P.cabs;
     a.bscale = P.bscale;
     a.n = (int)P.n;
     a.ks = (int)P.ks;
-    a.ncb = (int)P.ncb;
+    a.ncb = (int)(prec == RR_PREC_GRAM_BF16 ? P.ncb_gram : P.ncb);
     a.scale = (float)P.scale;
     a.two_kappa = b.two_kappa;
     a.csq = b.csq;
@@ -515,6 +533,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
     rr_status s = ensure_ws(P, cand_cap, acc_cap, band_cap, chunk * wpd, &w);
     if (s != RR_OK) return s;
     if ((s = ensure_streams(P, 4 * nchunks + 5)) != RR_OK) return s;
+    if (prec == RR_PREC_GRAM_BF16 && (s = ensure_gram(P, st)) != RR_OK) return s;
     const Bound b = bound_constants(P, prec);
     const Tune tn = tune ? *tune : tune_for(P, prec, exact, N, st);
     const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
@@ -704,6 +723,7 @@ void rr_free(rr_problem* p) {
     hipFree(P.op_f32);
     hipFree(P.op_i8);
     hipFree(P.bscale);
+    hipFree(P.op_gram);
     hipFree(P.cabs);
     hipFree(P.ws);
     for (hipEvent_t e : P.events) hipEventDestroy(e);
@@ -784,6 +804,10 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
     hipStream_t st = (hipStream_t)stream;
     const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
     if (d_M32) {
+        if (precision == RR_PREC_GRAM_BF16) {
+            const rr_status s = ensure_gram(P, st);
+            if (s != RR_OK) return s;
+        }
         const Bound b = bound_constants(P, precision);
         uint32_t* bits = nullptr;
         RR_HIP(hipMalloc(&bits, sizeof(uint32_t) * 8 * P.S * K));

@@ -57,8 +57,8 @@ std::mutex g_mu;
 std::map<Key, Entry> g_cache;
 bool g_loaded = false;
 
-int cost_log2(const Problem& P) {
-    uint64_t c = (uint64_t)P.ks * (uint64_t)P.ncb;
+int cost_log2(const Problem& P, int prec) {
+    uint64_t c = (uint64_t)P.ks * (uint64_t)(prec == RR_PREC_GRAM_BF16 ? P.ncb_gram : P.ncb);
     int l = 0;
     while (c > 1) {
         c >>= 1;
@@ -123,7 +123,7 @@ Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t
     if (exact || !tuning_enabled()) return def;
     std::lock_guard<std::mutex> g(g_mu);
     if (!g_loaded) load_file();
-    const Key key(prec, P.S, cost_log2(P));
+    const Key key(prec, P.S, cost_log2(P, prec));
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
         // entries read from a file may come from another build: keep them within the fit
@@ -134,7 +134,9 @@ Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t
     if (work_draws < (1u << 20)) return def;
 
     // probe pool: ~2^42 MFMA flops, 2^18 .. 2^20 draws
-    const double flops_per_draw = 2.0 * 16.0 * (double)P.ks * 32.0 * (double)P.ncb * (prec == RR_PREC_SPLIT_BF16 ? 2.0 : 1.0);
+    const double ncb = (double)(prec == RR_PREC_GRAM_BF16 ? P.ncb_gram : P.ncb);
+    const double flops_per_draw =
+        2.0 * 16.0 * (double)P.ks * 32.0 * ncb * (prec == RR_PREC_SPLIT_BF16 || prec == RR_PREC_GRAM_BF16 ? 2.0 : 1.0);
     uint64_t N = (uint64_t)(std::ldexp(1.0, 42) / std::max(1.0, flops_per_draw));
     N = std::min<uint64_t>(std::max<uint64_t>(N, 1u << 18), 1u << 20);
     const double q = 1e-3;

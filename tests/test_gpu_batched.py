@@ -67,9 +67,9 @@ def _single(rr, P, seed, N, mode, qa, prec):
     return u64(keys), M.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", ["split", "fp32", "i8"])
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8", "gram"])
 def test_batched_equals_single_quantile(rr, prec):
-    pr = {"split": rr.PREC_SPLIT_BF16, "fp32": rr.PREC_FP32, "i8": rr.PREC_FIXED_I8}[prec]
+    pr = {"split": rr.PREC_SPLIT_BF16, "fp32": rr.PREC_FP32, "i8": rr.PREC_FIXED_I8, "gram": rr.PREC_GRAM_BF16}[prec]
     N, q = 20_000, 0.01
     say(f"batched vs single, quantile, {prec}")
     Xs, Ps, seeds = _problems(rr, SHAPES)

@@ -41,7 +41,7 @@ def dev(x):
 
 
 PRECS = {"split": lambda rr: rr.PREC_SPLIT_BF16, "fp32": lambda rr: rr.PREC_FP32,
-         "i8": lambda rr: rr.PREC_FIXED_I8}
+         "i8": lambda rr: rr.PREC_FIXED_I8, "gram": lambda rr: rr.PREC_GRAM_BF16}
 
 
 def u64(t):
@@ -80,8 +80,8 @@ def test_regenerate_exact_ranks(rr):
 
 
 @pytest.mark.parametrize("n,n1,d,ridge", [(20, 10, 3, 0.0), (60, 25, 8, 0.0), (100, 50, 100, 1e-2),
-                                          (300, 150, 40, 0.0), (1000, 500, 1000, 1e-2)])
-@pytest.mark.parametrize("prec", ["split", "fp32", "i8"])
+                                          (300, 150, 40, 0.0), (1000, 500, 1000, 1e-2), (96, 40, 300, 1.0)])
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8", "gram"])
 def test_balance_values_and_bound(rr, n, n1, d, ridge, prec):
     say(f"balance n={n} d={d} prec={prec}")
     X = inputs.gaussian_X(n, d, 3)
@@ -98,6 +98,9 @@ def test_balance_values_and_bound(rr, n, n1, d, ridge, prec):
     if prec == "i8":
         # 15-bit fixed point: about 2^-13 sqrt(d / M) relative (the bound below is the contract)
         np.testing.assert_allclose(m32, want, rtol=5e-4 * np.sqrt(d / np.minimum(want, d)).max(), atol=1e-6 * d)
+    elif prec == "gram":
+        # w^T K w in FP32 can cancel; the bound below is the contract
+        np.testing.assert_allclose(m32, want, rtol=1e-3, atol=1e-5 * d)
     else:
         np.testing.assert_allclose(m32, want, rtol=1e-4, atol=1e-4 * d * 1e-3)
     assert np.all(np.abs(m32.astype(np.float64) - m64) <= err)
@@ -115,12 +118,12 @@ def _check_pool(rr, X, n1, ridge, seed, N, mode, qa, prec):
     Mg, fl = M.cpu().numpy(), flags.cpu().numpy().astype(bool)
     np.testing.assert_allclose(Mg[fl], Macc[fl], rtol=1e-9)
     np.testing.assert_allclose(Mg[~fl], Macc[~fl], rtol=1e-4)
-    if prec == "i8":
-        assert fl.all()   # the fixed-point form reports FP64 M for every accepted draw
+    if prec in ("i8", "gram"):
+        assert fl.all()   # these forms report FP64 M for every accepted draw
     return P, got, rr.rr_last_timing()
 
 
-@pytest.mark.parametrize("prec", ["split", "fp32", "i8"])
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8", "gram"])
 @pytest.mark.parametrize("mode,qa", [("quantile", 0.05), ("quantile", 1e-3), ("threshold", 4.0)])
 def test_pool_small(rr, prec, mode, qa):
     say(f"pool small {mode} {qa} {prec}")
@@ -210,7 +213,7 @@ def test_errors(rr):
     assert e.value.status == "RR_E_ARG"
 
 
-@pytest.mark.parametrize("prec", ["split", "fp32", "i8"])
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8", "gram"])
 def test_diagonal_metric_pool(rr, prec):
     """Standardise-only metric: same kernels on the column-scaled covariates."""
     say(f"diagonal metric pool {prec}")
@@ -239,7 +242,7 @@ def test_pool_large_n(rr, n, d, N):
     """n above 2048: 16 chunks of 256 units, generated with a runtime chunk count."""
     say(f"pool large n={n} d={d} N={N}")
     X = inputs.gaussian_X(n, d, n + 3)
-    for prec in ("split", "fp32", "i8"):
+    for prec in ("split", "fp32", "i8", "gram"):
         _check_pool(rr, X, n // 2 - 7, 1e-3, 99, N, "quantile", 0.02, prec)
 
 
@@ -276,3 +279,19 @@ def test_chi2_threshold_mode(rr):
     with pytest.raises(rr.RRError) as e:
         rr.rr_draw_balance(P, 5, 0, N, rr.MODE_CHI2_QUANTILE, 0.0, rr.PREC_SPLIT_BF16)
     assert e.value.status == "RR_E_ARG"
+
+
+@pytest.mark.parametrize("prec", ["split", "gram"])
+def test_high_dim_diagonal_pool(rr, prec):
+    """d > n under the standardise-only metric, where the Gram form does n^2 work per draw."""
+    say(f"high-dimensional diagonal pool n=200 d=768 {prec}")
+    X = inputs.gaussian_X(200, 768, 4242)
+    P = rr.rr_prepare(dev(X), 100, 0.0, metric=rr.METRIC_DIAGONAL)
+    N = 20_000
+    keys, M, flags = rr.rr_draw_balance(P, 8, 0, N, rr.MODE_QUANTILE, 0.01, PRECS[prec](rr))
+    acc, Macc, _ = pipeline.draw_balance(X, 100, 0.0, 8, 0, N, "quantile", 0.01, metric="diagonal")
+    np.testing.assert_array_equal(u64(keys), acc)
+    Mg, fl = M.cpu().numpy(), flags.cpu().numpy().astype(bool)
+    np.testing.assert_allclose(Mg[fl], Macc[fl], rtol=1e-9)
+    np.testing.assert_allclose(Mg[~fl], Macc[~fl], rtol=1e-4)
+    say(f"  accepted {len(acc)}, band {rr.rr_last_timing()['band']}")
