@@ -8,6 +8,9 @@ pass of the whole path over one synthetic problem: rr_prepare (whitening), rr_dr
 
 Workload (default): n = 1000, n1 = 500, d = 1000 iid N(0, 1) covariates, ridge 1e-2,
 1e8 Philox draws, q = 1.2e-5 (1200 accepted).  Inputs are resident in HBM before timing.
+Other workloads: --workload batched_512 (512 uneven pools in one graph launch) and
+--workload highdim_n256_d768 (d > n under the standardise-only metric, the Gram form against
+the W X~ forms).
 
 Prints one JSON line.  --gpus above 1 exits with an error: this path runs on one GPU.
 """
@@ -22,6 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "balance-checked draws/sec at n=d=1000: BF16-split MFMA vs FP32, same accept set"
+METRIC_GRAM = ("balance-checked draws/sec at n=256, d=768 (standardise-only metric): Gram form vs W X~ "
+               "forms, same accept set")
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 (matrix / vector)
 PEAK_INT8_TOPS = 5000.0        # MI355X dense int8 MFMA
@@ -64,7 +69,7 @@ def cpu_baseline(X, w, sample):
         cores = len(os.sched_getaffinity(0))
     keys = np.arange(sample, dtype=np.uint64)
     t0 = time.perf_counter()
-    M = pipeline.balance_of_keys(X, w["n1"], w["ridge_rel"], w["seed"], keys)
+    M = pipeline.balance_of_keys(X, w["n1"], w["ridge_rel"], w["seed"], keys, metric=w.get("metric", "mahalanobis"))
     accept.accept_quantile(keys, M, accept.quantile_count(w["q"], sample))
     dt = time.perf_counter() - t0
     return {"value": sample / dt, "unit": "draws/s", "cores": int(cores), "kind": "oracle",
@@ -182,8 +187,12 @@ def main():
     Xd = torch.from_numpy(X).to(dev)
     taus = w["taus"]
 
-    def step(Yd, obs, prec=rr.PREC_SPLIT_BF16):
-        P = rr.rr_prepare(Xd, n1, w["ridge_rel"])
+    gram = w["precision"] == "gram_bf16"
+    main_prec = rr.PREC_GRAM_BF16 if gram else rr.PREC_SPLIT_BF16
+    metric_id = rr.METRIC_DIAGONAL if w.get("metric") == "diagonal" else rr.METRIC_MAHALANOBIS
+
+    def step(Yd, obs, prec=main_prec):
+        P = rr.rr_prepare(Xd, n1, w["ridge_rel"], metric=metric_id)
         keys, M, flags = rr.rr_draw_balance(P, w["seed"], w["key_begin"], N, rr.MODE_QUANTILE, q, prec)
         t = rr.rr_last_timing()
         counts = None
@@ -218,18 +227,34 @@ def main():
     value = N / (ms_per_step / 1000.0)
     keys_split = keys_s.cpu().numpy()
 
-    flops_per_draw = 4.0 * n * d            # hi and lo products of the dense W X~ contraction
+    # hi and lo products of the dense W X~ contraction (the Gram form: W K, K = X~ X~^T n x n)
+    flops_per_draw = 4.0 * n * (n if gram else d)
     avg_launch_ms = contract_ms / max(launches, 1)
     achieved = flops_per_draw * N * args.steps / (contract_ms / 1000.0) / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_BF16_TFLOPS, "traffic": measured_traffic(),
-                "kernel": "contract_kernel<split BF16> (W X~ on 32x32x16 BF16 MFMA + reduce + prefilter)",
+                "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None if gram else measured_traffic(),
+                "kernel": ("contract_kernel<Gram BF16> (W K on 32x32x16 BF16 MFMA + w^T (W K) + prefilter)" if gram else
+                           "contract_kernel<split BF16> (W X~ on 32x32x16 BF16 MFMA + reduce + prefilter)"),
                 "avg_launch_ms": avg_launch_ms, "launches_per_step": launches / args.steps,
                 "algorithmic_flops_per_draw": flops_per_draw,
                 "gen_kernel_ms_per_step": gen_ms / args.steps}
 
+    split = None
+    if gram:
+        # the same step with the W X~ split form
+        step(Yd, obs, rr.PREC_SPLIT_BF16)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            _, keys_w, t, _ = step(Yd, obs, rr.PREC_SPLIT_BF16)
+        torch.cuda.synchronize()
+        msw = 1000.0 * (time.perf_counter() - t1) / args.steps
+        split = {"draws_per_s": N / (msw / 1000.0), "ms_per_step": msw,
+                 "same_accept_set": bool(np.array_equal(keys_w.cpu().numpy(), keys_split)),
+                 "gram_speedup": msw / ms_per_step}
+
     fp32 = None
-    if not args.no_fp32:
+    if not args.no_fp32 and not gram:
         P = rr.rr_prepare(Xd, n1, w["ridge_rel"])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -270,13 +295,14 @@ def main():
         base = cpu_baseline(X, w, args.cpu_sample)
 
     out = {
-        "metric": METRIC, "value": value, "unit": "draws/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC_GRAM if gram else METRIC, "value": value, "unit": "draws/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "n1": n1, "d": d, "num_draws": N, "q": q,
-                   "accepted": int(len(keys_split)), "ridge_rel": w["ridge_rel"], "precision": "split_bf16",
+                   "accepted": int(len(keys_split)), "ridge_rel": w["ridge_rel"], "precision": w["precision"],
+                   "metric": w.get("metric", "mahalanobis"),
                    "step": "rr_prepare + rr_draw_balance + rr_rand_test(201 nulls)"},
-        "roofline": roofline, "cpu_baseline": base, "fp32_form": fp32, "i8_form": i8,
+        "roofline": roofline, "cpu_baseline": base, "fp32_form": fp32, "i8_form": i8, "split_form": split,
         "contract_kernel_ms_per_step": contract_ms / args.steps, "guard_band": band,
         "rand_test_counts_min": int(counts.min().item()) if counts is not None else None,
     }

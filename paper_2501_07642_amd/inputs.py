@@ -73,6 +73,11 @@ WORKLOADS = {
         seed=0x5EED0004, key_begin=0, num_draws=100_000_000, mode="quantile", q=1.2e-5,
         precision="split_bf16", tau=0.5, noise_sd=1.0, y_seed=402,
         taus=list(np.linspace(-2.0, 2.0, 201)), obs_seed=403),
+    "highdim_n256_d768": dict(
+        kind="mc", n=256, n1=128, d=768, x="gaussian", x_seed=601, ridge_rel=0.0, metric="diagonal",
+        seed=0x5EED0006, key_begin=0, num_draws=100_000_000, mode="quantile", q=1e-4,
+        precision="gram_bf16", tau=0.5, noise_sd=1.0, y_seed=602,
+        taus=list(np.linspace(-2.0, 2.0, 201)), obs_seed=603),
     "batched_512": dict(
         kind="batched", num_problems=512, shape_seed=501, x_seed_base=10_000,
         ridge_rel=1e-2, seed_base=0x5EED0500, key_begin=0, num_draws=100_000,
