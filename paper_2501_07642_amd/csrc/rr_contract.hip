@@ -8,11 +8,12 @@
 // One workgroup (NW waves) takes a tile of 32 NW DB draws; wave w owns draws
 // [32 DB w, 32 DB (w+1)).  G^T = X~^T W^T is computed per covariate chunk of 32 CB: the A
 // operand (32 covariates x 16 units of X~^T) comes from the precomputed operand records,
-// staged from global memory straight into LDS four K steps at a time (double-buffered,
+// staged from global memory straight into LDS eight K steps at a time (double-buffered,
 // shared by the waves of the workgroup);
 // the B operand (16 units x 32 draws of W^T) is expanded from the tile's bitmasks in LDS.
 // In an output block, lane l holds draw l % 32 and 16 covariates, so ||G||^2 is reduced in
-// registers and across the two lane halves; the error bound needs only ||G||.
+// registers and across the two lane halves; the error bounds need only ||G|| (or, for the
+// Gram form, the sum of |G'_j| over the treated units).
 //
 //   split BF16: X~ = hi + lo, two 32x32x16 BF16 MFMA per K step into one FP32 accumulator;
 //   FP32:       32x32x2 FP32 MFMA; each K step starts from zero and is added on the VALU;
