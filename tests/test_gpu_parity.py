@@ -53,12 +53,10 @@ def keys_t(keys):
 
 
 # one n per 256-unit chunk count 1..8 (the generators specialise on it) plus the largest n
-@pytest.mark.parametrize("n,n1", [(1, 0), (5, 2), (20, 10), (64, 31), (100, 50), (257, 100), (600, 300),
+@pytest.mark.parametrize("n,n1", [(2, 1), (5, 2), (20, 10), (64, 31), (100, 50), (257, 100), (600, 300),
                                   (1000, 500), (1100, 550), (1400, 699), (1700, 851), (2000, 1000),
                                   (4096, 2048)])
 def test_regenerate_bits_exact(rr, n, n1):
-    if n1 == 0:
-        pytest.skip("n1 must be at least 1")
     say(f"regenerate n={n} n1={n1}")
     X = inputs.gaussian_X(n, 3, 1)
     P = rr.rr_prepare(dev(X), n1, 1e-2)
@@ -295,3 +293,12 @@ def test_high_dim_diagonal_pool(rr, prec):
     np.testing.assert_allclose(Mg[fl], Macc[fl], rtol=1e-9)
     np.testing.assert_allclose(Mg[~fl], Macc[~fl], rtol=1e-4)
     say(f"  accepted {len(acc)}, band {rr.rr_last_timing()['band']}")
+
+
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8", "gram"])
+def test_pool_extreme_n1(rr, prec):
+    """One treated unit, and one control unit, in every operand form."""
+    X = inputs.gaussian_X(97, 6, 977)
+    for n1 in (1, 96):
+        say(f"pool n=97 n1={n1} {prec}")
+        _check_pool(rr, X, n1, 0.0, 31, 3000, "quantile", 0.02, prec)
