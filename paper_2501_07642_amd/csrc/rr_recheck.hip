@@ -14,12 +14,14 @@ namespace rr {
 // 0/1) X~ (n x d) on the FP64 matrix cores, in groups of 16 draws (v_mfma_f64_16x16x4f64:
 // A lane l holds W[draw l % 16][unit 4k + l / 16], B lane l holds X~[unit 4k + l / 16][column
 // l % 16], result item r of lane l is G[draw 4r + l / 16][column l % 16]).  A workgroup tile
-// is 1 group, or 4 groups for long lists (the guard bands of problems with d >= n - 1): then
-// each X~ fragment loaded feeds four MFMAs and X~ is read once per 64 draws, at the cost of
-// more registers and fewer, longer tiles.  The NW = 4 waves of a workgroup regenerate the
-// treated sets into LDS, then split the 16-column blocks; each wave adds G^2 of its blocks
-// per draw and the partial sums are reduced in a fixed order (16 lanes, then the waves in
-// index order), so the value depends neither on the launch shape nor on the tile size.
+// is 1 group, or 4 groups in the batched launches for pools of up to 512 units, whose bands
+// hold most draws of the problems with d >= n - 1: then each X~ fragment loaded feeds four
+// MFMAs and X~ is read once per 64 draws, at the cost of more registers and fewer, longer
+// tiles.  The NW = 4 waves of a workgroup regenerate the treated sets into LDS, then split
+// the 16-column blocks, four at a time per wave (four independent X~ loads and MFMA chains
+// per K step); each wave adds G^2 of its blocks per draw and the partial sums are reduced in
+// a fixed order (16 lanes, then the waves in index order), so the value depends neither on
+// the launch shape nor on the tile size.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 struct RecheckShared {
