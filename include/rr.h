@@ -167,9 +167,9 @@ rr_status rr_regenerate(rr_problem* p, uint64_t seed, int exact, const uint64_t*
 
 /*
  * rr_balance_keys -- M of given draws by both device paths, for verification.
- *   d_M32, d_err  device, K floats each (may be null): the FP32 value of the W X~
- *                 contraction in the given precision and its rigorous error bound, so
- *                 |M32 - M| <= err;
+ *   d_M32, d_err  device, K floats each (may be null): the FP32 value of the contraction
+ *                 in the given precision (any RR_PREC_*, as for rr_draw_balance) and its
+ *                 rigorous error bound, so |M32 - M| <= err;
  *   d_M64         device, K doubles (may be null): the FP64 recomputation.
  */
 rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys,
