@@ -144,7 +144,7 @@ def test_exact_enumeration_c1(rr):
     say("exact enumeration n=20")
     X = inputs.workload_X("exact_n20_d3")
     P = rr.rr_prepare(dev(X), w["n1"], 0.0)
-    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32, rr.PREC_FIXED_I8):
+    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32, rr.PREC_FIXED_I8, rr.PREC_GRAM_BF16):
         keys, M, flags = rr.rr_draw_exact(P, rr.MODE_QUANTILE, w["q"], prec)
         acc, Macc, _ = pipeline.draw_exact(X, w["n1"], 0.0, "quantile", w["q"])
         assert len(acc) == 1848
@@ -251,7 +251,7 @@ def test_exact_enumeration_unbalanced(rr, mode, qa):
     X = inputs.gaussian_X(22, 4, 2201)
     P = rr.rr_prepare(dev(X), 6, 0.0)
     md = rr.MODE_QUANTILE if mode == "quantile" else rr.MODE_THRESHOLD
-    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32, rr.PREC_FIXED_I8):
+    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32, rr.PREC_FIXED_I8, rr.PREC_GRAM_BF16):
         keys, M, flags = rr.rr_draw_exact(P, md, qa, prec)
         acc, Macc, _ = pipeline.draw_exact(X, 6, 0.0, mode, qa)
         np.testing.assert_array_equal(u64(keys), acc)
@@ -268,7 +268,7 @@ def test_chi2_threshold_mode(rr):
     P = rr.rr_prepare(dev(X), 40, 0.0)
     q, N = 0.05, 20_000
     a = diagnose.c_q(q, 10)
-    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32, rr.PREC_FIXED_I8):
+    for prec in (rr.PREC_SPLIT_BF16, rr.PREC_FP32, rr.PREC_FIXED_I8, rr.PREC_GRAM_BF16):
         keys, M, flags = rr.rr_draw_balance(P, 5, 0, N, rr.MODE_CHI2_QUANTILE, q, prec)
         acc, Macc, _ = pipeline.draw_balance(X, 40, 0.0, 5, 0, N, "threshold", a)
         np.testing.assert_array_equal(u64(keys), acc)
