@@ -32,6 +32,55 @@ struct RecheckShared {
 
 constexpr int recheck_waves(int) { return 4; }
 
+// Column blocks cb0 + j NW, j < NB, of one wave: G^2 summed into part[q][r] (lane (g, c):
+// draw 16 q + 4 r + g, column c of the block).
+template <int NB, int G, int NW>
+__device__ __forceinline__ void recheck_cols(const RecheckArgs& a, const uint32_t* bits, int WS, int cb0, int nk,
+                                             int ngroups, int g, int c, double (&part)[G][4]) {
+    const double* xcol[NB];
+    bool cval[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int col = 16 * (cb0 + j * NW) + c;
+        cval[j] = col < a.d;
+        xcol[j] = a.X64 + (cval[j] ? col : 0);
+    }
+    f64x4 acc[NB][G];
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int q = 0; q < G; ++q) acc[j][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int kw = 0; kw < nk; ++kw) {
+        // 32 units = 8 K steps of 4; bitmask bits past n are zero
+        uint32_t word[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) word[q] = bits[(16 * q + c) * WS + kw];
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const int unit = 32 * kw + 4 * st + g;
+            double bv[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) bv[j] = (cval[j] && unit < a.n) ? xcol[j][(size_t)unit * a.d] : 0.0;
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                if (q < ngroups) {
+                    const double av = ((word[q] >> (4 * st + g)) & 1u) ? 1.0 : 0.0;
+#pragma unroll
+                    for (int j = 0; j < NB; ++j)
+                        acc[j][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[j], acc[j][q], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // columns past d hold zeros (their loads were masked)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part[q][r] = fma(acc[j][q][r], acc[j][q][r], part[q][r]);
+}
+
 // Entries e0 .. min(e0 + 16 G, cnt) - 1 of the list (workgroup-uniform arguments).
 template <int S, bool EXACT, int G>
 __device__ __forceinline__ void recheck_tile(const RecheckArgs& a, uint32_t e0, uint32_t cnt, RecheckShared sh) {
@@ -71,51 +120,18 @@ __device__ __forceinline__ void recheck_tile(const RecheckArgs& a, uint32_t e0, 
         const int ngroups = (nt + 15) / 16;
         double part[kRecheckGroups][4] = {};
         // A wave takes its column blocks CBW at a time (blocks cb0 + j NW), so that each K
-        // step issues CBW independent X~ loads and CBW x G independent MFMA chains.
+        // step issues up to CBW independent X~ loads and CBW x G independent MFMA chains; the
+        // last group of a wave may hold fewer blocks (nb), and blocks past ncolb issue neither
+        // loads nor MFMAs.
         constexpr int CBW = 4;
         for (int cb0 = wave; cb0 < ncolb; cb0 += NW * CBW) {
-            const double* xcol[CBW];
-            bool cval[CBW];
-#pragma unroll
-            for (int j = 0; j < CBW; ++j) {
-                const int col = 16 * (cb0 + j * NW) + c;
-                cval[j] = col < a.d;
-                xcol[j] = a.X64 + (cval[j] ? col : 0);
+            const int nb = min(CBW, (ncolb - cb0 + NW - 1) / NW);   // wave-uniform, >= 1
+            switch (nb) {
+                case 1: recheck_cols<1, G, NW>(a, sh.bits, WS, cb0, nk, ngroups, g, c, part); break;
+                case 2: recheck_cols<2, G, NW>(a, sh.bits, WS, cb0, nk, ngroups, g, c, part); break;
+                case 3: recheck_cols<3, G, NW>(a, sh.bits, WS, cb0, nk, ngroups, g, c, part); break;
+                default: recheck_cols<4, G, NW>(a, sh.bits, WS, cb0, nk, ngroups, g, c, part); break;
             }
-            f64x4 acc[CBW][kRecheckGroups];
-#pragma unroll
-            for (int j = 0; j < CBW; ++j)
-#pragma unroll
-                for (int q = 0; q < kRecheckGroups; ++q) acc[j][q] = f64x4{0.0, 0.0, 0.0, 0.0};
-            for (int kw = 0; kw < nk; ++kw) {
-                // 32 units = 8 K steps of 4; bitmask bits past n are zero
-                uint32_t word[kRecheckGroups];
-#pragma unroll
-                for (int q = 0; q < kRecheckGroups; ++q) word[q] = sh.bits[(16 * q + c) * WS + kw];
-#pragma unroll
-                for (int st = 0; st < 8; ++st) {
-                    const int unit = 32 * kw + 4 * st + g;
-                    double bv[CBW];
-#pragma unroll
-                    for (int j = 0; j < CBW; ++j) bv[j] = (cval[j] && unit < a.n) ? xcol[j][(size_t)unit * a.d] : 0.0;
-#pragma unroll
-                    for (int q = 0; q < kRecheckGroups; ++q) {
-                        if (q < ngroups) {
-                            const double av = ((word[q] >> (4 * st + g)) & 1u) ? 1.0 : 0.0;
-#pragma unroll
-                            for (int j = 0; j < CBW; ++j)
-                                acc[j][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[j], acc[j][q], 0, 0, 0);
-                        }
-                    }
-                }
-            }
-            // blocks past ncolb hold zeros (their loads were masked)
-#pragma unroll
-            for (int j = 0; j < CBW; ++j)
-#pragma unroll
-                for (int q = 0; q < kRecheckGroups; ++q)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) part[q][r] = fma(acc[j][q][r], acc[j][q][r], part[q][r]);
         }
         // part[q][r] of lane (g, c): draw 16 q + 4 r + g, column c of this wave's blocks
 #pragma unroll
