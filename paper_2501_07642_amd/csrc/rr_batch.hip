@@ -3,8 +3,9 @@
 //
 // Work list.  Pools are grouped by S (256-unit chunks per draw, which fixes the bitmask
 // layout and the kernel instantiation) and, inside a group, ordered by MFMA work per draw
-// (ks x ncb), largest first.  Draws are processed in rounds of C draws per pool (C bounds the
-// bitmask buffers); in every round, for every group, a persistent generation launch walks the
+// (ks x ncb), largest first.  Draws are processed in rounds of up to C draws per pool (C
+// bounds the bitmask buffers; the first and the last round are about C / 4, since nothing
+// overlaps them); in every round, for every group, a persistent generation launch walks the
 // (pool, draw) list and a persistent contraction launch walks the (pool, tile) list, the
 // generation of the next group / round overlapping the contraction of the current one on a
 // second stream.  The contraction writes, per draw, the FP32 bounds [lo, hi] and m32
@@ -31,7 +32,11 @@ namespace rr {
 
 constexpr int kFinishSort = 2048;              // accepted keys sorted in LDS per pool
 constexpr uint32_t kBatchBandCap = 1u << 14;   // guard-band entries per pool (d < n - 1)
-constexpr size_t kBitsBudget = size_t(1) << 30;   // bytes per bitmask round buffer
+// Bytes per bitmask round buffer.  It sets the round length C: the contraction stream trails
+// the generation stream by one (group, round) item, so shorter rounds start and end the
+// overlap sooner; 512 MB (about 21 rounds over the 512-pool workload) measured 3% faster
+// than 1 GB, and 256 MB slower again from the kernel count.
+constexpr size_t kBitsBudget = size_t(1) << 29;
 // Recheck workgroups per CU: the bands of a bitmask class (up to kBatchBandCap entries per
 // pool; up to every draw where d >= n - 1, since there M hardly varies across draws under a
 // small ridge and most draws sit within the error bound of the boundary) form one flat list
@@ -323,7 +328,29 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     uint64_t C = std::max<uint64_t>(512, kBitsBudget / (4 * words_per_draw));
     C = std::min<uint64_t>(C / 512 * 512, N);
     for (Group& g : groups) g.bits_off *= C;
-    const uint64_t R = (N + C - 1) / C;
+    // Round schedule: the first round's generation runs with no contraction beside it and
+    // the last round's contraction with no generation, so both are cut to about C / 4
+    // (multiples of 512); the rounds between are C draws each, and none exceeds C.
+    std::vector<uint64_t> rbeg, rcnt;
+    {
+        const uint64_t C0 = std::max<uint64_t>(512, C / 4 / 512 * 512);
+        uint64_t at = 0;
+        auto push = [&](uint64_t c) {
+            rbeg.push_back(at);
+            rcnt.push_back(c);
+            at += c;
+        };
+        if (N > 2 * C0) push(C0);
+        while (N - at > C + C0) push(C);
+        const uint64_t rest = N - at;
+        if (rest > C || rest > 2 * C0) {   // rest <= C + C0 here, so rest - C0 <= C
+            push(rest - C0);
+            push(C0);
+        } else if (rest > 0) {
+            push(rest);
+        }
+    }
+    const uint64_t R = rbeg.size();
     const uint32_t acc_cap = (uint32_t)(mode == RR_MODE_QUANTILE ? k : std::min<uint64_t>(capacity, N));
     // guard-band capacity per pool, packed back to back
     std::vector<uint32_t> bcap((size_t)nprob);
@@ -406,7 +433,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             const Problem& Q = P[i]->P;
             const ContractArgs proto = make_contract_args(Q, precision, bound_constants(Q, precision));
             for (uint64_t r = 0; r < R; ++r) {
-                const uint64_t d0 = r * C, cnt = std::min<uint64_t>(C, N - d0);
+                const uint64_t d0 = rbeg[r], cnt = rcnt[r];
                 const size_t slot = r * np + gpos[gi] + j;
                 uint32_t* bits = d_bits[r & 1] + g.bits_off + j * C * 8 * g.S;
                 GenArgs ga{};
@@ -529,7 +556,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         check(hipEventRecord(fork, B.s_main));
         check(hipStreamWaitEvent(B.s_gen, fork, 0));
         for (uint64_t r = 0; r < R && e == hipSuccess; ++r) {
-            const uint64_t cnt = std::min<uint64_t>(C, N - r * C);
+            const uint64_t cnt = rcnt[r];
             for (size_t gi = 0; gi < groups.size(); ++gi) {
                 const Group& g = groups[gi];
                 const uint64_t m = g.idx.size();
