@@ -89,10 +89,12 @@ void contract_kernel(ContractArgs a0) {
     // priority measured slower, so batched launches keep the default.)
     if constexpr (!BATCH) __builtin_amdgcn_s_setprio(3);
     // Batched launches walk the (problem, tile) list of all pools; the list is ordered
-    // longest problem first, so the grid-stride assignment balances uneven problems.
+    // longest problem first, so the grid-stride assignment balances uneven problems, and the
+    // workgroups of one XCD take neighbouring tiles of each stride window, so that an XCD's
+    // L2 holds the operands of a few pools rather than of every pool in flight.
     const uint64_t ntiles = BATCH ? (uint64_t)a0.nprob * a0.tpp : (a0.num + TILE - 1) / TILE;
 
-    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (uint64_t t = BATCH ? xcd_slot(blockIdx.x, gridDim.x) : blockIdx.x; t < ntiles; t += gridDim.x) {
         const ContractArgs& a = BATCH ? a0.tab[t / a0.tpp] : a0;
         const uint64_t tile0 = (BATCH ? t % a0.tpp : t) * TILE;
         const int nchunks = a.ncb / CB;

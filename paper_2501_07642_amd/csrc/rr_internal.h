@@ -39,6 +39,17 @@ constexpr int kRecordU4I8 = 64;       // fixed-point int8 records: 1 plane x 64 
 constexpr int kQMax = 16319;
 constexpr int kQMin = -16320;
 constexpr int kMaxS = RR_MAX_N / kUnitsPerChunk;   // 16
+// Zeroed doubles after X~ (n x d, row-major): the FP64 recheck's lanes for columns past d
+// read up to 15 values beyond the end of their row, which for the last row lands here.
+constexpr int64_t kX64Pad = 16;
+constexpr uint32_t kXcds = 8;          // accelerator dies; workgroups are dealt to them round robin
+
+// Position of workgroup b inside each grid-stride window of g items, such that the g / 8
+// workgroups on one XCD (b mod 8) take neighbouring items: a permutation of [0, g) when g is a
+// multiple of 8, else the identity.
+__host__ __device__ inline uint32_t xcd_slot(uint32_t b, uint32_t g) {
+    return g % kXcds == 0 ? (b % kXcds) * (g / kXcds) + b / kXcds : b;
+}
 
 // Host-side description of a prepared problem.
 struct Problem {

@@ -367,7 +367,8 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
             return fail(RR_E_DEVICE);                                                     \
         }                                                                                 \
     } while (0)
-    RR_PHIP(hipMalloc(&P.X64, sizeof(double) * n * d));
+    RR_PHIP(hipMalloc(&P.X64, sizeof(double) * (n * d + kX64Pad)));
+    RR_PHIP(hipMemsetAsync(P.X64 + n * d, 0, sizeof(double) * kX64Pad, st));
     RR_PHIP(hipMalloc(&P.L, sizeof(double) * d * d));
     RR_PHIP(hipMalloc(&P.mu, sizeof(double) * d));
     RR_PHIP(hipMalloc(&P.op_split, sizeof(uint4) * kRecordU4 * P.ks * P.ncb));

@@ -18,8 +18,9 @@ namespace rr {
 // hold most draws of the problems with d >= n - 1: then each X~ fragment loaded feeds four
 // MFMAs and X~ is read once per 64 draws, at the cost of more registers and fewer, longer
 // tiles.  The NW = 4 waves of a workgroup regenerate the treated sets into LDS, then split
-// the 16-column blocks, four at a time per wave (four independent X~ loads and MFMA chains
-// per K step); each wave adds G^2 of its blocks per draw and the partial sums are reduced in
+// the 16-column blocks, up to four at a time per wave (up to four independent MFMA chains,
+// with the X~ loads of a whole bitmask word issued one word ahead); each wave adds G^2 of
+// its blocks per draw and the partial sums are reduced in
 // a fixed order (16 lanes, then the waves in index order), so the value depends neither on
 // the launch shape nor on the tile size.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -37,48 +38,67 @@ constexpr int recheck_waves(int) { return 4; }
 template <int NB, int G, int NW>
 __device__ __forceinline__ void recheck_cols(const RecheckArgs& a, const uint32_t* bits, int WS, int cb0, int nk,
                                              int ngroups, int g, int c, double (&part)[G][4]) {
-    const double* xcol[NB];
+    typedef const __attribute__((address_space(1))) double* gptr;
     bool cval[NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const int col = 16 * (cb0 + j * NW) + c;
-        cval[j] = col < a.d;
-        xcol[j] = a.X64 + (cval[j] ? col : 0);
-    }
+    for (int j = 0; j < NB; ++j) cval[j] = 16 * (cb0 + j * NW) + c < a.d;
     f64x4 acc[NB][G];
 #pragma unroll
     for (int j = 0; j < NB; ++j)
 #pragma unroll
         for (int q = 0; q < G; ++q) acc[j][q] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int kw = 0; kw < nk; ++kw) {
-        // 32 units = 8 K steps of 4; bitmask bits past n are zero
+    // The X~ values of one 32-unit bitmask word (8 K steps x NB blocks) are loaded as one
+    // batch, unconditionally, and the next word's batch is issued before this word's MFMAs,
+    // so a wave waits for memory about once per word rather than once per K step.  A K step
+    // takes one row address; its blocks are fixed offsets from it.  Rows past n read row
+    // n - 1 (their bits are zero, so they add nothing).  Lanes of columns past d read on past
+    // the end of their row (at most 15 values; after the last row, into the zeroed padding
+    // of X~): B column c only feeds result column c, which those lanes hold and leave out of
+    // the sum of squares.
+    const double* x0 = a.X64 + 16 * cb0 + c;
+    const int nlast = a.n - 1;
+    const size_t ld = (size_t)a.d;
+    double buf0[8][NB], buf1[8][NB];
+    auto load = [&](double (&b)[8][NB], int kw) {
+#pragma unroll
+        for (int st = 0; st < 8; ++st) {
+            const gptr p = (gptr)(x0 + (size_t)min(32 * kw + 4 * st + g, nlast) * ld);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) b[st][j] = p[16 * NW * j];
+        }
+    };
+    auto step = [&](const double (&b)[8][NB], int kw) {
         uint32_t word[G];
 #pragma unroll
         for (int q = 0; q < G; ++q) word[q] = bits[(16 * q + c) * WS + kw];
 #pragma unroll
-        for (int st = 0; st < 8; ++st) {
-            const int unit = 32 * kw + 4 * st + g;
-            double bv[NB];
-#pragma unroll
-            for (int j = 0; j < NB; ++j) bv[j] = (cval[j] && unit < a.n) ? xcol[j][(size_t)unit * a.d] : 0.0;
+        for (int st = 0; st < 8; ++st)
 #pragma unroll
             for (int q = 0; q < G; ++q) {
-                if (q < ngroups) {
+                if (q < ngroups) {   // groups past the tile's draws (wave-uniform)
                     const double av = ((word[q] >> (4 * st + g)) & 1u) ? 1.0 : 0.0;
 #pragma unroll
                     for (int j = 0; j < NB; ++j)
-                        acc[j][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[j], acc[j][q], 0, 0, 0);
+                        acc[j][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[st][j], acc[j][q], 0, 0, 0);
                 }
             }
-        }
+    };
+    load(buf0, 0);
+    int kw = 0;
+    for (; kw + 1 < nk; kw += 2) {
+        load(buf1, kw + 1);
+        step(buf0, kw);
+        load(buf0, min(kw + 2, nk - 1));
+        step(buf1, kw + 1);
     }
-    // columns past d hold zeros (their loads were masked)
+    if (kw < nk) step(buf0, kw);
 #pragma unroll
     for (int j = 0; j < NB; ++j)
 #pragma unroll
         for (int q = 0; q < G; ++q)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) part[q][r] = fma(acc[j][q][r], acc[j][q][r], part[q][r]);
+            for (int r = 0; r < 4; ++r)
+                if (cval[j]) part[q][r] = fma(acc[j][q][r], acc[j][q][r], part[q][r]);
 }
 
 // Entries e0 .. min(e0 + 16 G, cnt) - 1 of the list (workgroup-uniform arguments).
