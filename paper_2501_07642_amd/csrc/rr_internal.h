@@ -376,6 +376,42 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
     // moves lo to p (c < n1) or hi to p - 1 (c >= n1).
     uint32_t lo = 0u, hi = 0xFFFFFFFFu;
     int clo = 0, chi = n;
+    if constexpr (S <= 2) {
+        // At most 8 values per lane: a 256-bin histogram of the top byte (the 1 KB list as
+        // counters) gives the first bracket, [b * 2^24, (b + 1) * 2^24 - 1] with b the first
+        // bin whose running count reaches n1, in one counting pass; with uniform keys it
+        // holds one or two values.
+        uint32_t* h = reinterpret_cast<uint32_t*>(list);
+        list[2 * lane] = make_uint2(0u, 0u);
+        list[2 * lane + 1] = make_uint2(0u, 0u);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (s < chunks && ((vm[s][r] >> lane) & 1ull)) atomicAdd(&h[u[s][r] >> 24], 1u);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint2 ha = list[2 * lane], hb = list[2 * lane + 1];   // bins 4 lane .. 4 lane + 3
+        const uint32_t c1 = ha.x, c2 = c1 + ha.y, c3 = c2 + hb.x, c4 = c3 + hb.y;
+        const uint32_t incl = wave_incl_scan(c4);                  // values in bins < 4 lane + 4
+        const uint32_t excl = incl - c4;
+        const int L = (int)__builtin_ctzll(ballot(incl >= (uint32_t)n1));
+        const uint32_t need = (uint32_t)n1 - (uint32_t)__shfl((int)excl, L, 64);   // >= 1
+        const uint32_t d1 = (uint32_t)__shfl((int)c1, L, 64), d2 = (uint32_t)__shfl((int)c2, L, 64),
+                       d3 = (uint32_t)__shfl((int)c3, L, 64), d4 = (uint32_t)__shfl((int)c4, L, 64);
+        const int k = need <= d1 ? 0 : (need <= d2 ? 1 : (need <= d3 ? 2 : 3));
+        const uint32_t before = k == 0 ? 0u : (k == 1 ? d1 : (k == 2 ? d2 : d3));
+        const uint32_t upto = k == 0 ? d1 : (k == 1 ? d2 : (k == 2 ? d3 : d4));
+        const uint32_t ex = (uint32_t)__shfl((int)excl, L, 64);
+        const uint32_t b = 4u * (uint32_t)L + (uint32_t)k;
+        lo = b << 24;
+        hi = lo | 0xFFFFFFu;
+        clo = (int)(ex + before);
+        chi = (int)(ex + upto);
+        __builtin_amdgcn_wave_barrier();
+    }
     // stop at <= 8 bracket values after a few cheap counts, at <= 64 after many
     for (int it = 0; (chi - clo > 64 || (chi - clo > 8 && it < 6)) && lo < hi; ++it) {
         const uint32_t span = hi - lo;
