@@ -145,6 +145,22 @@ def run_batched(args, rr, inputs, np, torch):
         "prepare_s_all_pools": prep_s, "i8_form": i8}), flush=True)
 
 
+def run_alone(args, rr, torch, w, Xd):
+    """Generation and contraction without overlap: rr_balance_keys runs them one after the
+    other on one stream (no FP64 values), so a kernel trace shows each kernel's time alone."""
+    prec = {"split": rr.PREC_SPLIT_BF16, "fp32": rr.PREC_FP32, "i8": rr.PREC_FIXED_I8}[args.alone]
+    P = rr.rr_prepare(Xd, w["n1"], w["ridge_rel"])
+    keys = torch.arange(1 << 20, dtype=torch.int64, device="cuda:0")
+    for it in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rr.rr_balance_keys(P, w["seed"], keys, prec, want_m64=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"alone": args.alone, "workload": args.workload, "keys": 1 << 20, "iteration": it,
+                          "wall_ms": 1000.0 * dt}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +174,9 @@ def main():
     ap.add_argument("--no-i8", action="store_true", help="skip the fixed-point int8 comparison leg")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (PMC byte-counter scale)")
+    ap.add_argument("--alone", choices=["split", "fp32", "i8"], default=None,
+                    help="instead of the benchmark: generation and contraction one after the other "
+                         "(rr_balance_keys on 2^20 keys of the workload's pool, 3 times), for kernel traces")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this hot path runs on one GPU; --gpus {args.gpus} is not supported "
@@ -186,6 +205,8 @@ def main():
     X = inputs.workload_X(args.workload)
     Xd = torch.from_numpy(X).to(dev)
     taus = w["taus"]
+    if args.alone:
+        return run_alone(args, rr, torch, w, Xd)
 
     gram = w["precision"] == "gram_bf16"
     main_prec = rr.PREC_GRAM_BF16 if gram else rr.PREC_SPLIT_BF16

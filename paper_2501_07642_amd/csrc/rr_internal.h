@@ -195,7 +195,7 @@ struct rr_problem {
 
 namespace rr {
 // Host functions shared by the translation units.
-hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t st);
+hipError_t launch_gen(int S, bool exact, int prec, const GenArgs& g, int grid, hipStream_t st);
 hipError_t launch_gen_batch(int S, const GenArgs* tab, uint64_t nprob, uint64_t per, int grid, hipStream_t st);
 hipError_t launch_contract(int S, int prec, int db, bool batch, const ContractArgs& a, int grid, hipStream_t st);
 int contract_tile(int prec, int S, int db);
@@ -298,7 +298,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // (block, 0, lo32(key), hi32(key)) and the pool seed as Philox key.
 //
 // Selection (exact): the n1-th smallest value u* is bracketed by [lo, hi] with
-// #{u < lo} < n1 <= #{u <= hi}; counts come from wave ballots.  Pivots interpolate inside
+// #{u < lo} < n1 <= #{u <= hi}; counts come from wave ballots.  With HIST the first bracket
+// is one top-byte bin of a 256-bin LDS histogram of the keys.  Pivots interpolate inside
 // the bracket for the first steps (unit keys are uniform, so two or three steps leave a few
 // values), then bisect, so the loop ends after at most 4 + 33 steps for any input.  The
 // <= 64 values left in the bracket are ranked in LDS; values equal to u* are taken in unit
@@ -308,8 +309,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 //
 // C > 0 fixes the number of 256-unit chunks (ceil(n / 256)) at compile time: the per-chunk
 // validity tests fold away and only the last chunk keeps a runtime lane mask; C = 0 takes
-// it from n at run time.
-template <int S, int C = 0>
+// it from n at run time.  HIST changes only the cost, never the selected set.
+template <int S, int C = 0, bool HIST = (S <= 8)>
 __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint2* list,
                                             uint32_t* out) {
     static_assert(C >= 0 && C <= S, "chunk count within the bitmask layout");
@@ -376,11 +377,11 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
     // moves lo to p (c < n1) or hi to p - 1 (c >= n1).
     uint32_t lo = 0u, hi = 0xFFFFFFFFu;
     int clo = 0, chi = n;
-    if constexpr (S <= 2) {
-        // At most 8 values per lane: a 256-bin histogram of the top byte (the 1 KB list as
-        // counters) gives the first bracket, [b * 2^24, (b + 1) * 2^24 - 1] with b the first
-        // bin whose running count reaches n1, in one counting pass; with uniform keys it
-        // holds one or two values.
+    if constexpr (HIST) {
+        // A 256-bin histogram of the keys' top byte (the 1 KB list as LDS counters) gives the
+        // first bracket, [b * 2^24, (b + 1) * 2^24 - 1] with b the first bin whose running
+        // count reaches n1, in one counting pass; with uniform keys it holds about n / 256
+        // values, so the count loop below has little or nothing left to do.
         uint32_t* h = reinterpret_cast<uint32_t*>(list);
         list[2 * lane] = make_uint2(0u, 0u);
         list[2 * lane + 1] = make_uint2(0u, 0u);
@@ -541,26 +542,26 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
 }
 
 // gen_mc_bits with the chunk count of n fixed at compile time (S / 2 < chunks <= S).
-template <int S>
+template <int S, bool HIST = (S <= 8)>
 __device__ __forceinline__ void gen_mc_bits_fixed(uint64_t seed, uint64_t key, int n, int n1, uint2* list,
                                                   uint32_t* out) {
     const int chunks = (n + kUnitsPerChunk - 1) / kUnitsPerChunk;
     if constexpr (S == 1) {
-        gen_mc_bits<1, 1>(seed, key, n, n1, list, out);
+        gen_mc_bits<1, 1, HIST>(seed, key, n, n1, list, out);
     } else if constexpr (S == 2) {
-        gen_mc_bits<2, 2>(seed, key, n, n1, list, out);
+        gen_mc_bits<2, 2, HIST>(seed, key, n, n1, list, out);
     } else if constexpr (S == 4) {
-        if (chunks == 4) gen_mc_bits<4, 4>(seed, key, n, n1, list, out);
-        else gen_mc_bits<4, 3>(seed, key, n, n1, list, out);
+        if (chunks == 4) gen_mc_bits<4, 4, HIST>(seed, key, n, n1, list, out);
+        else gen_mc_bits<4, 3, HIST>(seed, key, n, n1, list, out);
     } else if constexpr (S == 8) {
         switch (chunks) {
-            case 8: gen_mc_bits<8, 8>(seed, key, n, n1, list, out); break;
-            case 7: gen_mc_bits<8, 7>(seed, key, n, n1, list, out); break;
-            case 6: gen_mc_bits<8, 6>(seed, key, n, n1, list, out); break;
-            default: gen_mc_bits<8, 5>(seed, key, n, n1, list, out); break;
+            case 8: gen_mc_bits<8, 8, HIST>(seed, key, n, n1, list, out); break;
+            case 7: gen_mc_bits<8, 7, HIST>(seed, key, n, n1, list, out); break;
+            case 6: gen_mc_bits<8, 6, HIST>(seed, key, n, n1, list, out); break;
+            default: gen_mc_bits<8, 5, HIST>(seed, key, n, n1, list, out); break;
         }
     } else {
-        gen_mc_bits<S, 0>(seed, key, n, n1, list, out);
+        gen_mc_bits<S, 0, HIST>(seed, key, n, n1, list, out);
     }
 }
 
