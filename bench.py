@@ -13,6 +13,9 @@ Other workloads: --workload batched_512 (512 uneven pools in one graph launch) a
 the W X~ forms).
 
 Prints one JSON line.  --gpus above 1 exits with an error: this path runs on one GPU.
+--alone {split,fp32,i8} replaces the benchmark with three rr_balance_keys calls on 2^20 keys
+of the workload's pool (generation, then contraction, on one stream), for kernel traces of
+each kernel on its own.
 """
 
 import argparse
