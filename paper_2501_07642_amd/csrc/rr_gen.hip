@@ -13,7 +13,7 @@ namespace rr {
 // Register caps that keep three generation waves on every SIMD beside two contraction waves:
 // up to 1024 units 64 registers (beside contraction waves of up to 168), up to 2048 units 96
 // (beside the 1-block tiles of about 112; a few bytes spill).
-template <int S, bool EXACT, bool HIST = (S <= 8)>
+template <int S, bool EXACT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 8 : (S == 8 ? 5 : 1)))) void gen_kernel(GenArgs g) {
     __shared__ uint2 slist[4][128];
     const int wave = threadIdx.x >> 6, lane = lane_id();
@@ -32,17 +32,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 8 
     } else {
         for (uint64_t idx = gw; idx < g.num; idx += nw) {
             const uint64_t key = g.keylist ? g.keylist[idx] : g.key_begin + idx;
-            gen_mc_bits_fixed<S, HIST>(g.seed, key, g.n, g.n1, slist[wave], g.out + idx * (8 * S));
+            gen_mc_bits_fixed<S>(g.seed, key, g.n, g.n1, slist[wave], g.out + idx * (8 * S));
             __builtin_amdgcn_wave_barrier();
         }
     }
 }
 
-// The histogram bracket makes generation itself faster for every S <= 8, but for n in
-// (512, 1024] beside the BF16 and FP32 contractions (which stage their operands through LDS)
-// it measured about 1% fewer draws/s overall, against 5% more beside the int8 contraction;
-// those launches keep the count-only selection.
-hipError_t launch_gen(int S, bool exact, int prec, const GenArgs& g, int grid, hipStream_t st) {
+hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t st) {
     grid = std::max(1, grid);
     if (exact) {
         hipLaunchKernelGGL((gen_kernel<1, true>), dim3(grid), dim3(256), 0, st, g);
@@ -50,12 +46,7 @@ hipError_t launch_gen(int S, bool exact, int prec, const GenArgs& g, int grid, h
         switch (S) {
             case 1: hipLaunchKernelGGL((gen_kernel<1, false>), dim3(grid), dim3(256), 0, st, g); break;
             case 2: hipLaunchKernelGGL((gen_kernel<2, false>), dim3(grid), dim3(256), 0, st, g); break;
-            case 4:
-                if (prec == RR_PREC_FIXED_I8)
-                    hipLaunchKernelGGL((gen_kernel<4, false, true>), dim3(grid), dim3(256), 0, st, g);
-                else
-                    hipLaunchKernelGGL((gen_kernel<4, false, false>), dim3(grid), dim3(256), 0, st, g);
-                break;
+            case 4: hipLaunchKernelGGL((gen_kernel<4, false>), dim3(grid), dim3(256), 0, st, g); break;
             case 8: hipLaunchKernelGGL((gen_kernel<8, false>), dim3(grid), dim3(256), 0, st, g); break;
             case 16: hipLaunchKernelGGL((gen_kernel<16, false>), dim3(grid), dim3(256), 0, st, g); break;
             default: return hipErrorInvalidValue;
@@ -102,7 +93,7 @@ int gen_kernel_vgprs(int S, bool batch) {
 #define RR_CASE(SV)                                                                              \
     case SV:                                                                                     \
         e = batch ? hipFuncGetAttributes(&fa, (const void*)gen_batch_kernel<SV>)                 \
-                  : hipFuncGetAttributes(&fa, (const void*)gen_kernel<SV, false, (SV != 4 && SV <= 8)>); \
+                  : hipFuncGetAttributes(&fa, (const void*)gen_kernel<SV, false>);               \
         break;
         RR_CASE(1)
         RR_CASE(2)

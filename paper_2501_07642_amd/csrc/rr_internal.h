@@ -195,7 +195,7 @@ struct rr_problem {
 
 namespace rr {
 // Host functions shared by the translation units.
-hipError_t launch_gen(int S, bool exact, int prec, const GenArgs& g, int grid, hipStream_t st);
+hipError_t launch_gen(int S, bool exact, const GenArgs& g, int grid, hipStream_t st);
 hipError_t launch_gen_batch(int S, const GenArgs* tab, uint64_t nprob, uint64_t per, int grid, hipStream_t st);
 hipError_t launch_contract(int S, int prec, int db, bool batch, const ContractArgs& a, int grid, hipStream_t st);
 int contract_tile(int prec, int S, int db);
@@ -298,8 +298,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // (block, 0, lo32(key), hi32(key)) and the pool seed as Philox key.
 //
 // Selection (exact): the n1-th smallest value u* is bracketed by [lo, hi] with
-// #{u < lo} < n1 <= #{u <= hi}; counts come from wave ballots.  With HIST the first bracket
-// is one top-byte bin of a 256-bin LDS histogram of the keys.  Pivots interpolate inside
+// #{u < lo} < n1 <= #{u <= hi}; counts come from wave ballots.  For n <= 2048 the first
+// bracket is one top-byte bin of a 256-bin LDS histogram of the keys.  Pivots interpolate inside
 // the bracket for the first steps (unit keys are uniform, so two or three steps leave a few
 // values), then bisect, so the loop ends after at most 4 + 33 steps for any input.  The
 // <= 64 values left in the bracket are ranked in LDS; values equal to u* are taken in unit
@@ -309,8 +309,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 //
 // C > 0 fixes the number of 256-unit chunks (ceil(n / 256)) at compile time: the per-chunk
 // validity tests fold away and only the last chunk keeps a runtime lane mask; C = 0 takes
-// it from n at run time.  HIST changes only the cost, never the selected set.
-template <int S, int C = 0, bool HIST = (S <= 8)>
+// it from n at run time.
+template <int S, int C = 0>
 __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint2* list,
                                             uint32_t* out) {
     static_assert(C >= 0 && C <= S, "chunk count within the bitmask layout");
@@ -377,7 +377,7 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
     // moves lo to p (c < n1) or hi to p - 1 (c >= n1).
     uint32_t lo = 0u, hi = 0xFFFFFFFFu;
     int clo = 0, chi = n;
-    if constexpr (HIST) {
+    if constexpr (S <= 8) {
         // A 256-bin histogram of the keys' top byte (the 1 KB list as LDS counters) gives the
         // first bracket, [b * 2^24, (b + 1) * 2^24 - 1] with b the first bin whose running
         // count reaches n1, in one counting pass; with uniform keys it holds about n / 256
@@ -398,19 +398,18 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
         const uint32_t c1 = ha.x, c2 = c1 + ha.y, c3 = c2 + hb.x, c4 = c3 + hb.y;
         const uint32_t incl = wave_incl_scan(c4);                  // values in bins < 4 lane + 4
         const uint32_t excl = incl - c4;
+        // L: the lane holding bin b (wave-uniform); only its values below are read, the other
+        // lanes' (need may wrap there) are discarded
         const int L = (int)__builtin_ctzll(ballot(incl >= (uint32_t)n1));
-        const uint32_t need = (uint32_t)n1 - (uint32_t)__shfl((int)excl, L, 64);   // >= 1
-        const uint32_t d1 = (uint32_t)__shfl((int)c1, L, 64), d2 = (uint32_t)__shfl((int)c2, L, 64),
-                       d3 = (uint32_t)__shfl((int)c3, L, 64), d4 = (uint32_t)__shfl((int)c4, L, 64);
-        const int k = need <= d1 ? 0 : (need <= d2 ? 1 : (need <= d3 ? 2 : 3));
-        const uint32_t before = k == 0 ? 0u : (k == 1 ? d1 : (k == 2 ? d2 : d3));
-        const uint32_t upto = k == 0 ? d1 : (k == 1 ? d2 : (k == 2 ? d3 : d4));
-        const uint32_t ex = (uint32_t)__shfl((int)excl, L, 64);
-        const uint32_t b = 4u * (uint32_t)L + (uint32_t)k;
+        const uint32_t need = (uint32_t)n1 - excl;                  // >= 1 in lane L
+        const uint32_t k = need <= c1 ? 0u : (need <= c2 ? 1u : (need <= c3 ? 2u : 3u));
+        const uint32_t before = k == 0u ? 0u : (k == 1u ? c1 : (k == 2u ? c2 : c3));
+        const uint32_t upto = k == 0u ? c1 : (k == 1u ? c2 : (k == 2u ? c3 : c4));
+        const uint32_t b = 4u * (uint32_t)L + __builtin_amdgcn_readlane(k, L);
         lo = b << 24;
         hi = lo | 0xFFFFFFu;
-        clo = (int)(ex + before);
-        chi = (int)(ex + upto);
+        clo = (int)__builtin_amdgcn_readlane(excl + before, L);
+        chi = (int)__builtin_amdgcn_readlane(excl + upto, L);
         __builtin_amdgcn_wave_barrier();
     }
     // stop at <= 8 bracket values after a few cheap counts, at <= 64 after many
@@ -542,26 +541,26 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
 }
 
 // gen_mc_bits with the chunk count of n fixed at compile time (S / 2 < chunks <= S).
-template <int S, bool HIST = (S <= 8)>
+template <int S>
 __device__ __forceinline__ void gen_mc_bits_fixed(uint64_t seed, uint64_t key, int n, int n1, uint2* list,
                                                   uint32_t* out) {
     const int chunks = (n + kUnitsPerChunk - 1) / kUnitsPerChunk;
     if constexpr (S == 1) {
-        gen_mc_bits<1, 1, HIST>(seed, key, n, n1, list, out);
+        gen_mc_bits<1, 1>(seed, key, n, n1, list, out);
     } else if constexpr (S == 2) {
-        gen_mc_bits<2, 2, HIST>(seed, key, n, n1, list, out);
+        gen_mc_bits<2, 2>(seed, key, n, n1, list, out);
     } else if constexpr (S == 4) {
-        if (chunks == 4) gen_mc_bits<4, 4, HIST>(seed, key, n, n1, list, out);
-        else gen_mc_bits<4, 3, HIST>(seed, key, n, n1, list, out);
+        if (chunks == 4) gen_mc_bits<4, 4>(seed, key, n, n1, list, out);
+        else gen_mc_bits<4, 3>(seed, key, n, n1, list, out);
     } else if constexpr (S == 8) {
         switch (chunks) {
-            case 8: gen_mc_bits<8, 8, HIST>(seed, key, n, n1, list, out); break;
-            case 7: gen_mc_bits<8, 7, HIST>(seed, key, n, n1, list, out); break;
-            case 6: gen_mc_bits<8, 6, HIST>(seed, key, n, n1, list, out); break;
-            default: gen_mc_bits<8, 5, HIST>(seed, key, n, n1, list, out); break;
+            case 8: gen_mc_bits<8, 8>(seed, key, n, n1, list, out); break;
+            case 7: gen_mc_bits<8, 7>(seed, key, n, n1, list, out); break;
+            case 6: gen_mc_bits<8, 6>(seed, key, n, n1, list, out); break;
+            default: gen_mc_bits<8, 5>(seed, key, n, n1, list, out); break;
         }
     } else {
-        gen_mc_bits<S, 0, HIST>(seed, key, n, n1, list, out);
+        gen_mc_bits<S, 0>(seed, key, n, n1, list, out);
     }
 }
 

@@ -582,7 +582,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         g.out = w.bits[bsel];
         RR_HIP(hipEventRecord(ev_t[4 * c + 2], P.gen_stream));
         const uint64_t gen_units = exact ? (num + 63) / 64 : num;
-        RR_HIP(launch_gen(P.S, exact, prec, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * tn.gen_wg),
+        RR_HIP(launch_gen(P.S, exact, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * tn.gen_wg),
                           P.gen_stream));
         RR_HIP(hipEventRecord(ev_t[4 * c + 3], P.gen_stream));
         RR_HIP(hipEventRecord(ev_ready[bsel], P.gen_stream));
@@ -821,7 +821,7 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
         g.out = bits;
         const int cus = device_cus(P.device);
         const uint64_t gen_units = exact ? (K + 63) / 64 : K;
-        hipError_t e = launch_gen(P.S, exact != 0, precision, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * kGenWgPerCu), st);
+        hipError_t e = launch_gen(P.S, exact != 0, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * kGenWgPerCu), st);
         ContractArgs a = make_contract_args(P, precision, b);
         a.bits = bits;
         a.num = K;
