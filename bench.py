@@ -13,7 +13,7 @@ Other workloads: --workload batched_512 (512 uneven pools in one graph launch) a
 the W X~ forms).
 
 Prints one JSON line.  --gpus above 1 exits with an error: this path runs on one GPU.
---alone {split,fp32,i8} replaces the benchmark with three rr_balance_keys calls on 2^20 keys
+--alone {split,fp32,i8,gram} replaces the benchmark with three rr_balance_keys calls on 2^20 keys
 of the workload's pool (generation, then contraction, on one stream), for kernel traces of
 each kernel on its own.
 """
@@ -151,8 +151,10 @@ def run_batched(args, rr, inputs, np, torch):
 def run_alone(args, rr, torch, w, Xd):
     """Generation and contraction without overlap: rr_balance_keys runs them one after the
     other on one stream (no FP64 values), so a kernel trace shows each kernel's time alone."""
-    prec = {"split": rr.PREC_SPLIT_BF16, "fp32": rr.PREC_FP32, "i8": rr.PREC_FIXED_I8}[args.alone]
-    P = rr.rr_prepare(Xd, w["n1"], w["ridge_rel"])
+    prec = {"split": rr.PREC_SPLIT_BF16, "fp32": rr.PREC_FP32, "i8": rr.PREC_FIXED_I8,
+            "gram": rr.PREC_GRAM_BF16}[args.alone]
+    metric_id = rr.METRIC_DIAGONAL if w.get("metric") == "diagonal" else rr.METRIC_MAHALANOBIS
+    P = rr.rr_prepare(Xd, w["n1"], w["ridge_rel"], metric=metric_id)
     keys = torch.arange(1 << 20, dtype=torch.int64, device="cuda:0")
     for it in range(3):
         torch.cuda.synchronize()
@@ -177,7 +179,7 @@ def main():
     ap.add_argument("--no-i8", action="store_true", help="skip the fixed-point int8 comparison leg")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (PMC byte-counter scale)")
-    ap.add_argument("--alone", choices=["split", "fp32", "i8"], default=None,
+    ap.add_argument("--alone", choices=["split", "fp32", "i8", "gram"], default=None,
                     help="instead of the benchmark: generation and contraction one after the other "
                          "(rr_balance_keys on 2^20 keys of the workload's pool, 3 times), for kernel traces")
     args = ap.parse_args()
