@@ -292,6 +292,22 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+// Inclusive prefix sum across the wave without LDS traffic: shifted adds inside each 16-lane
+// row through DPP (row_shr 1, 2, 4, 8; lanes shifted in from outside the row read 0), then
+// the totals of the lower rows, read from lanes 15, 31 and 47 into scalar registers.
+__device__ __forceinline__ uint32_t wave_incl_scan_rows(uint32_t v) {
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);
+    const int t0 = __builtin_amdgcn_readlane(x, 15), t1 = __builtin_amdgcn_readlane(x, 31),
+              t2 = __builtin_amdgcn_readlane(x, 47);
+    const int lane = lane_id();
+    x += (lane >= 16 ? t0 : 0) + (lane >= 32 ? t1 : 0) + (lane >= 48 ? t2 : 0);
+    return (uint32_t)x;
+}
+
 // ---------------------------------------------------------------------------------------
 // Monte Carlo draw: the n1 units with the smallest (u_i, i) become treated.  Unit
 // i = 256 s + 64 r + lane reads word r of Philox block 64 s + lane under counter
@@ -396,7 +412,7 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
         __builtin_amdgcn_wave_barrier();
         const uint2 ha = list[2 * lane], hb = list[2 * lane + 1];   // bins 4 lane .. 4 lane + 3
         const uint32_t c1 = ha.x, c2 = c1 + ha.y, c3 = c2 + hb.x, c4 = c3 + hb.y;
-        const uint32_t incl = wave_incl_scan(c4);                  // values in bins < 4 lane + 4
+        const uint32_t incl = wave_incl_scan_rows(c4);             // values in bins < 4 lane + 4
         const uint32_t excl = incl - c4;
         // L: the lane holding bin b (wave-uniform); only its values below are read, the other
         // lanes' (need may wrap there) are discarded
@@ -479,10 +495,10 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
         }
         const bool is_t = lane < cnt && lt < need && need <= le;
         const uint64_t mt = ballot(is_t);
-        const int src = (int)__builtin_ctzll(mt);
-        ustar = __shfl(mine, src, 64);
-        const int lts = __shfl(lt, src, 64);
-        const int les = __shfl(le, src, 64);
+        const int src = (int)__builtin_ctzll(mt);   // wave-uniform: lane reads, not shuffles
+        ustar = __builtin_amdgcn_readlane(mine, src);
+        const int lts = __builtin_amdgcn_readlane(lt, src);
+        const int les = __builtin_amdgcn_readlane(le, src);
         take = need - lts;
         eq_total = les - lts;
         __builtin_amdgcn_wave_barrier();
