@@ -428,8 +428,10 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
         chi = (int)__builtin_amdgcn_readlane(excl + upto, L);
         __builtin_amdgcn_wave_barrier();
     }
-    // stop at <= 8 bracket values after a few cheap counts, at <= 64 after many
-    for (int it = 0; (chi - clo > 64 || (chi - clo > 8 && it < 6)) && lo < hi; ++it) {
+    // stop at <= 8 bracket values after a few cheap counts, at <= 64 after many; after the
+    // histogram bracket (n <= 2048), at <= 64 at once: ranking a few more values in LDS is
+    // cheaper than another count pass over 4 S keys per lane
+    for (int it = 0; (chi - clo > 64 || (S > 8 && chi - clo > 8 && it < 6)) && lo < hi; ++it) {
         const uint32_t span = hi - lo;
         uint32_t off;
         if (it < 4) {
