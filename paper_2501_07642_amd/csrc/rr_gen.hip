@@ -63,11 +63,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 8 
     __shared__ uint2 slist[4][128];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave, nw = (uint64_t)gridDim.x * 4;
+    // (pool p, draw i) of idx, carried along the grid stride without a 64-bit division per draw
+    uint64_t p = gw / per, i = gw - p * per;
     for (uint64_t idx = gw; idx < total; idx += nw) {
-        const uint64_t p = idx / per, i = idx - p * per;
         const GenArgs& g = tab[p];
         gen_mc_bits_fixed<S>(g.seed, g.key_begin + i, g.n, g.n1, slist[wave], g.out + i * (8 * S));
         __builtin_amdgcn_wave_barrier();
+        i += nw;
+        while (i >= per) {
+            i -= per;
+            ++p;
+        }
     }
 }
 
