@@ -198,6 +198,22 @@ rr_status rr_rand_test(rr_problem* p, uint64_t seed, int exact, const uint64_t* 
                        double* h_tau_hat, void* stream);
 
 /*
+ * rr_rand_test_interval -- rr_rand_test plus the fiducial interval obtained by inverting the
+ * test over the null grid (section 2.3: randomization_test's optional inversion returns a
+ * fiducial interval; section 4).  The paper fixes neither the level nor the shape; here the
+ * interval is the set of grid values tau0_g whose p-value c_g / K exceeds alpha:
+ *   h_interval   host, 2 doubles: [min, max] of those tau0_g (both NaN when none is kept);
+ *   h_contiguous host: 1 when the kept grid points are contiguous in the caller's grid order
+ *                (or none is kept), 0 when the kept set has gaps (a non-convex region).
+ * Other arguments and outputs as rr_rand_test; G >= 1 and 0 < alpha < 1 (RR_E_ARG otherwise).
+ */
+rr_status rr_rand_test_interval(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys,
+                                uint64_t K, uint64_t obs_index, const double* d_Y,
+                                const double* h_tau0, int64_t G, double alpha,
+                                uint64_t* d_counts, double* h_tau_hat, double* h_interval,
+                                int* h_contiguous, void* stream);
+
+/*
  * rr_draw_balance_batched -- many independent Monte Carlo pools in one persistent launch
  * (section 2.1 "Batched processing").  Problem i uses handle P[i], seed seeds[i], draws
  * [key_begin, key_begin + num_draws) and the same mode / q_or_a / precision for all.
@@ -237,6 +253,18 @@ rr_status rr_diagnose(int64_t n1, int64_t n0, int64_t d, double q, double sigma,
  * already meets the target.  Errors: RR_E_ARG; RR_E_RANGE when no q >= q_lo meets it. */
 rr_status rr_q_star(int64_t n1, int64_t n0, int64_t d, double sigma, double r2, double tau,
                     double alpha, double power, double q_lo, double* q_star);
+
+/* Realised RMSE of the difference in means for an accepted assignment with balance statistic M
+ * (chi^2_d scale, as reported by rr_draw_balance), under the linear outcome model of section 2.2
+ * with noise sd sigma and R^2 = r2, sigma_prog^2 = r2 / (1 - r2) sigma^2 and the paper's
+ * imbalance ||Delta||^2 = (1/n1 + 1/n0) M (Appendix A part A):
+ *   rmse_typical = sqrt(sigma^2 (1/n1 + 1/n0) + sigma_prog^2 ||Delta||^2 / d), the expected squared
+ *                  bias over prognostic directions uniform on the sphere (typical orientation);
+ *   rmse_bound   = sqrt(sigma^2 (1/n1 + 1/n0) + sigma_prog^2 ||Delta||^2), the Cauchy-Schwarz bound
+ *                  (the prognostic direction aligned with the imbalance).
+ * Errors: RR_E_ARG (as rr_diagnose; M negative or not finite). */
+rr_status rr_realized_rmse(int64_t n1, int64_t n0, int64_t d, double M, double sigma, double r2,
+                           double* rmse_typical, double* rmse_bound);
 
 /* Timing of the last rr_draw_balance / rr_draw_exact / rr_draw_balance_batched call on
  * this thread: host wall milliseconds of the call, and HIP-event milliseconds summed over the

@@ -19,17 +19,6 @@ path contracts, so that the two algebras check each other.
 import numpy as np
 
 
-def mahalanobis(X, w, S_lam):
-    """M for one 0/1 assignment vector w."""
-    X = np.asarray(X, dtype=np.float64)
-    w = np.asarray(w).astype(bool)
-    n = X.shape[0]
-    n1 = int(w.sum())
-    n0 = n - n1
-    delta = X[w].mean(axis=0) - X[~w].mean(axis=0)
-    return float(n1 * n0 / n * delta @ np.linalg.solve(S_lam, delta))
-
-
 def mahalanobis_batch(X, W, S_lam):
     """M for every row of a 0/1 matrix W (B x n) with a common n1."""
     X = np.asarray(X, dtype=np.float64)

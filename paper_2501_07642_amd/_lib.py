@@ -29,10 +29,13 @@ SIGNATURES = [
     ("rr_regenerate", _I, [_P, _U64, _I, _P, _U64, _P, _P]),
     ("rr_balance_keys", _I, [_P, _U64, _I, _P, _U64, _I, _P, _P, _P, _P]),
     ("rr_rand_test", _I, [_P, _U64, _I, _P, _U64, _U64, _P, _P, _I64, _P, C.POINTER(_D), _P]),
+    ("rr_rand_test_interval", _I, [_P, _U64, _I, _P, _U64, _U64, _P, _P, _I64, _D, _P, C.POINTER(_D), _P,
+                                   C.POINTER(_I), _P]),
     ("rr_draw_balance_batched", _I, [_P, _I64, _P, _U64, _U64, _I, _D, _I, _P, _P, _U64, _P, _P]),
     ("rr_last_timing", _I, [C.POINTER(_D), C.POINTER(_D), C.POINTER(_D), C.POINTER(_I64), C.POINTER(_U64)]),
     ("rr_diagnose", _I, [_I64, _I64, _I64, _D, _D, _D, _P]),
     ("rr_q_star", _I, [_I64, _I64, _I64, _D, _D, _D, _D, _D, _D, C.POINTER(_D)]),
+    ("rr_realized_rmse", _I, [_I64, _I64, _I64, _D, _D, _D, C.POINTER(_D), C.POINTER(_D)]),
 ]
 
 
@@ -221,6 +224,24 @@ def rr_rand_test(P, seed, keys, obs_index, Y, tau0, exact=False):
     return counts[:G], th.value
 
 
+def rr_rand_test_interval(P, seed, keys, obs_index, Y, tau0, alpha=0.05, exact=False):
+    """Returns (counts, tau_hat, (lo, hi), contiguous): the test plus its inversion over the grid."""
+    torch = _torch()
+    keys = keys.contiguous()
+    Y = Y.contiguous()
+    tau = [float(t) for t in tau0]
+    G = len(tau)
+    taus = (C.c_double * max(G, 1))(*tau)
+    counts = torch.empty(max(G, 1), dtype=torch.int64, device=keys.device)
+    th = C.c_double()
+    ci = (C.c_double * 2)()
+    contig = C.c_int()
+    _check(load().rr_rand_test_interval(P.handle, seed, int(exact), _ptr(keys), keys.numel(), obs_index, _ptr(Y),
+                                        C.cast(taus, C.c_void_p), G, float(alpha), _ptr(counts), C.byref(th),
+                                        C.cast(ci, C.c_void_p), C.byref(contig), _stream()))
+    return counts[:G], th.value, (ci[0], ci[1]), bool(contig.value)
+
+
 def rr_draw_balance_batched(problems, seeds, key_begin, num_draws, mode=MODE_QUANTILE, q_or_a=0.01,
                             precision=PREC_SPLIT_BF16, capacity=None):
     """Returns a list of (keys, M) per problem."""
@@ -255,6 +276,13 @@ def rr_diagnose(n1, n0, d, q, sigma=1.0, r2=0.0):
     out = _Design()
     _check(load().rr_diagnose(n1, n0, d, float(q), float(sigma), float(r2), C.cast(C.byref(out), C.c_void_p)))
     return {name: getattr(out, name) for name, _ in _Design._fields_}
+
+
+def rr_realized_rmse(n1, n0, d, M, sigma=1.0, r2=0.0):
+    """(typical-orientation RMSE, Cauchy-Schwarz bound) of an assignment with balance M (chi^2 scale)."""
+    t, b = C.c_double(), C.c_double()
+    _check(load().rr_realized_rmse(n1, n0, d, float(M), float(sigma), float(r2), C.byref(t), C.byref(b)))
+    return t.value, b.value
 
 
 def rr_q_star(n1, n0, d, sigma, r2, tau, alpha=0.05, power=0.8, q_lo=1e-300):

@@ -518,7 +518,10 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     sig.push_back((uint64_t)(uintptr_t)B.ws);
     sig.push_back(C);
     for (int64_t i = 0; i < nprob; ++i) {
-        sig.push_back((uint64_t)(uintptr_t)P[i]);
+        // the handle's process-unique id, not its address: a freed handle's address can be
+        // reused by a new problem of another shape, whose S group, tile grid and operands the
+        // captured launches would not match
+        sig.push_back(P[i]->P.uid);
         sig.push_back(seeds[i]);
         sig.push_back((uint64_t)(uintptr_t)d_keys[i]);
         sig.push_back((uint64_t)(uintptr_t)d_M[i]);

@@ -190,3 +190,19 @@ extern "C" rr_status rr_q_star(int64_t n1, int64_t n0, int64_t d, double sigma, 
     *q_star = std::exp(lo);
     return RR_OK;
 }
+
+extern "C" rr_status rr_realized_rmse(int64_t n1, int64_t n0, int64_t d, double M, double sigma, double r2,
+                                      double* rmse_typical, double* rmse_bound) {
+    if (!rmse_typical || !rmse_bound || !valid_design(n1, n0, d, sigma, r2) || !(M >= 0.0) || !std::isfinite(M)) {
+        set_error("rr_realized_rmse: invalid argument");
+        return RR_E_ARG;
+    }
+    // the realised imbalance on the paper's scale, ||Delta||^2 = (1/n1 + 1/n0) M
+    const double sc = 1.0 / (double)n1 + 1.0 / (double)n0;
+    const double m_paper = sc * M;
+    const double noise = sigma * sigma * sc;                      // irreducible residual variance
+    const double prog = r2 / (1.0 - r2) * sigma * sigma;         // sigma_prog^2
+    *rmse_typical = std::sqrt(noise + prog / (double)d * m_paper);
+    *rmse_bound = std::sqrt(noise + prog * m_paper);
+    return RR_OK;
+}

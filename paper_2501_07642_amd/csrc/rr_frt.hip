@@ -12,14 +12,17 @@
 // A double tau0 is m 2^-E with m odd, so tau' = m 2^D, D = s - E, and the comparison
 // |alpha_k - m 2^D beta_k| >= |alpha_o - m 2^D beta_o| (both sides times 2^-D when D < 0)
 // is carried out in 128-bit integers.
+#include <algorithm>
 #include <cmath>
+#include <string>
+#include <vector>
 
 #include "rr_internal.h"
 
 namespace rr {
 
 __global__ __launch_bounds__(256) void frt_quantize_kernel(const double* Y, int n, int64_t* Yq, int64_t* meta) {
-    // meta[0] = s, meta[1] = sum Yq
+    // meta[0] = s, meta[1] = sum Yq, meta[2] = 0
     __shared__ double smax[256];
     __shared__ long long ssum[256];
     __shared__ int s_shift;
@@ -42,6 +45,7 @@ __global__ __launch_bounds__(256) void frt_quantize_kernel(const double* Y, int 
         }
         s_shift = sh;
         meta[0] = sh;
+        meta[2] = 0;   // range flag of the null values (set by frt_tau_kernel)
     }
     __syncthreads();
     long long acc = 0;
@@ -104,11 +108,43 @@ __global__ __launch_bounds__(256) void frt_stats_kernel(const uint64_t* keys, ui
 
 __device__ __forceinline__ __int128 abs128(__int128 x) { return x < 0 ? -x : x; }
 
+__device__ __forceinline__ int bitlen_dev(unsigned __int128 x) {
+    const uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
+    return hi ? 128 - __builtin_clzll(hi) : (lo ? 64 - __builtin_clzll(lo) : 0);
+}
+
+// Per null value g: tau0 = m 2^-E with m odd (m = 0 for tau0 = 0), D = s - E, and the range
+// check of the 128-bit comparison (|alpha| <= 2^62, |beta| <= n^2 / 4 + 1); a value outside
+// it sets meta[2], and then the count kernel writes nothing.
+__global__ void frt_tau_kernel(const double* tau, int64_t G, int n, int64_t* meta, int64_t* tm, int* tD) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const int s = (int)meta[0];
+    const double t = tau[g];
+    int64_t m = 0;
+    int D = 0;
+    if (t != 0.0) {
+        int e = 0;
+        const double f = frexp(t, &e);                    // t = f 2^e, |f| in [0.5, 1)
+        int64_t mant = (int64_t)ldexp(f, 53);             // exact: t = mant 2^(e - 53)
+        const int tz = __builtin_ctzll((uint64_t)(mant < 0 ? -mant : mant));
+        m = mant / ((int64_t)1 << tz);
+        D = s - (53 - e - tz);
+    }
+    const int bbits = bitlen_dev((unsigned __int128)((uint64_t)n * (uint64_t)n / 4 + 1));
+    const int mbits = bitlen_dev((unsigned __int128)(uint64_t)(m < 0 ? -m : m));
+    const bool ok = D >= 0 ? (mbits + D + bbits <= 125) : (62 - D <= 125 && mbits + bbits <= 125);
+    if (!ok) atomicOr((unsigned long long*)&meta[2], 1ull);
+    tm[g] = m;
+    tD[g] = D;
+}
+
 // One workgroup per null value g: counts |alpha_k - tau' beta_k| >= |alpha_o - tau' beta_o|.
 __global__ __launch_bounds__(256) void frt_count_kernel(const int64_t* alpha, const int64_t* beta, uint64_t K,
                                                         uint64_t obs, const int64_t* tm, const int* tD,
-                                                        uint64_t* counts) {
+                                                        const int64_t* meta, uint64_t* counts) {
     __shared__ unsigned long long red[256];
+    if (meta[2]) return;   // a null value out of range: the call fails and writes no counts
     const int g = blockIdx.x;
     const __int128 m = tm[g];
     const int D = tD[g];
@@ -152,16 +188,130 @@ static hipError_t launch_stats(int S, dim3 grid, hipStream_t st, const uint64_t*
     return hipGetLastError();
 }
 
-static int bitlen_u(unsigned __int128 x) {
-    int b = 0;
-    while (x) {
-        ++b;
-        x >>= 1;
-    }
-    return b;
+const uint64_t* binom_table_ext(int dev);
+
+// Scratch of one randomization test, carved from one device buffer (256-byte aligned parts):
+// meta (s, sum Yq, range flag), Yq (n), the observed bitmask (ceil(n / 32) words), alpha and
+// beta (K each), the null values and their (m, D) decompositions (G each).
+struct FrtScratch {
+    int64_t* meta;
+    int64_t* Yq;
+    uint32_t* obits;
+    int64_t* alpha;
+    int64_t* beta;
+    double* tau;
+    int64_t* tm;
+    int* tD;
+};
+
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t frt_scratch_bytes(int64_t n, uint64_t K, int64_t G) {
+    const size_t g = (size_t)std::max<int64_t>(G, 1);
+    return a256(4 * 8) + a256(8 * (size_t)n) + a256(4 * (size_t)((n + 31) / 32)) + 2 * a256(8 * (size_t)K) +
+           2 * a256(8 * g) + a256(4 * g);
 }
 
-const uint64_t* binom_table_ext(int dev);
+static FrtScratch frt_carve(void* base, int64_t n, uint64_t K, int64_t G) {
+    char* b = (char*)base;
+    const size_t g = (size_t)std::max<int64_t>(G, 1);
+    FrtScratch f;
+    f.meta = (int64_t*)b;
+    b += a256(4 * 8);
+    f.Yq = (int64_t*)b;
+    b += a256(8 * (size_t)n);
+    f.obits = (uint32_t*)b;
+    b += a256(4 * (size_t)((n + 31) / 32));
+    f.alpha = (int64_t*)b;
+    b += a256(8 * (size_t)K);
+    f.beta = (int64_t*)b;
+    b += a256(8 * (size_t)K);
+    f.tau = (double*)b;
+    b += a256(8 * g);
+    f.tm = (int64_t*)b;
+    b += a256(8 * g);
+    f.tD = (int*)b;
+    return f;
+}
+
+// Argument checks shared by the entry points (host, no device work).
+rr_status frt_check(rr_problem* p, int exact, const uint64_t* d_keys, uint64_t K, uint64_t obs_index,
+                    const double* d_Y, const double* h_tau0, int64_t G, uint64_t* d_counts, const char* who) {
+    if (!p || !d_keys || !d_Y || K == 0 || G < 0 || (G > 0 && (!h_tau0 || !d_counts))) {
+        set_error(std::string(who) + ": invalid argument");
+        return RR_E_ARG;
+    }
+    if (obs_index >= K) {
+        set_error(std::string(who) + ": observed index not among the accepted keys");
+        return RR_E_OBS;
+    }
+    if (exact && p->P.n > RR_MAX_N_EXACT) {
+        set_error(std::string(who) + ": exact keys need n <= 64");
+        return RR_E_RANGE;
+    }
+    for (int64_t g = 0; g < G; ++g)
+        if (!std::isfinite(h_tau0[g])) {
+            set_error(std::string(who) + ": tau0 must be finite");
+            return RR_E_ARG;
+        }
+    return RR_OK;
+}
+
+// The test on a caller-provided scratch buffer of frt_scratch_bytes(n, K, G) bytes: kernels on
+// `st`, one synchronisation at the end (for the range flag and tau_hat).  No allocation.
+rr_status frt_run(Problem& P, uint64_t seed, int exact, const uint64_t* d_keys, uint64_t K, uint64_t obs_index,
+                  const double* d_Y, const double* h_tau0, int64_t G, uint64_t* d_counts, double* h_tau_hat,
+                  hipStream_t st, void* scratch, const char* who) {
+    const int n = (int)P.n, n1 = (int)P.n1;
+    const uint64_t* binom = exact ? binom_table_ext(P.device) : nullptr;
+    const FrtScratch f = frt_carve(scratch, P.n, K, G);
+#define RR_FHIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            set_error(std::string(who) + ": " + #call + ": " + hipGetErrorString(e_));         \
+            return RR_E_DEVICE;                                                                \
+        }                                                                                      \
+    } while (0)
+    hipLaunchKernelGGL(frt_quantize_kernel, dim3(1), dim3(256), 0, st, d_Y, n, f.Yq, f.meta);
+    RR_FHIP(hipGetLastError());
+    // the observed draw's bitmask
+    const uint64_t* okey = d_keys + obs_index;
+    if (exact)
+        RR_FHIP(launch_stats<true>(P.S, dim3(1), st, okey, 1, seed, n, n1, binom, f.Yq, f.meta, nullptr, nullptr,
+                                   nullptr, f.obits));
+    else
+        RR_FHIP(launch_stats<false>(P.S, dim3(1), st, okey, 1, seed, n, n1, binom, f.Yq, f.meta, nullptr, nullptr,
+                                    nullptr, f.obits));
+    const dim3 grid((unsigned)std::min<uint64_t>((K + 3) / 4, 4096));
+    if (exact)
+        RR_FHIP(launch_stats<true>(P.S, grid, st, d_keys, K, seed, n, n1, binom, f.Yq, f.meta, f.obits, f.alpha,
+                                   f.beta, nullptr));
+    else
+        RR_FHIP(launch_stats<false>(P.S, grid, st, d_keys, K, seed, n, n1, binom, f.Yq, f.meta, f.obits, f.alpha,
+                                    f.beta, nullptr));
+    if (G > 0) {
+        RR_FHIP(hipMemcpyAsync(f.tau, h_tau0, sizeof(double) * G, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(frt_tau_kernel, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, st, f.tau, G, n, f.meta,
+                           f.tm, f.tD);
+        RR_FHIP(hipGetLastError());
+        hipLaunchKernelGGL(frt_count_kernel, dim3((unsigned)G), dim3(256), 0, st, f.alpha, f.beta, K, obs_index, f.tm,
+                           f.tD, f.meta, d_counts);
+        RR_FHIP(hipGetLastError());
+    }
+    int64_t hmeta[3] = {0, 0, 0};
+    int64_t halpha_o = 0;
+    RR_FHIP(hipMemcpyAsync(hmeta, f.meta, sizeof(hmeta), hipMemcpyDeviceToHost, st));
+    RR_FHIP(hipMemcpyAsync(&halpha_o, f.alpha + obs_index, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    RR_FHIP(hipStreamSynchronize(st));
+#undef RR_FHIP
+    if (hmeta[2]) {
+        set_error(std::string(who) + ": tau0 outside the exact comparison range");
+        return RR_E_RANGE;
+    }
+    if (h_tau_hat) *h_tau_hat = std::ldexp((double)halpha_o, -(int)hmeta[0]) / ((double)n1 * (double)(n - n1));
+    return RR_OK;
+}
 
 }  // namespace rr
 
@@ -170,122 +320,41 @@ using namespace rr;
 extern "C" rr_status rr_rand_test(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys, uint64_t K,
                                   uint64_t obs_index, const double* d_Y, const double* h_tau0, int64_t G,
                                   uint64_t* d_counts, double* h_tau_hat, void* stream) {
-    if (!p || !d_keys || !d_Y || K == 0 || G < 0 || (G > 0 && (!h_tau0 || !d_counts))) {
-        set_error("rr_rand_test: invalid argument");
+    rr_status s = frt_check(p, exact, d_keys, K, obs_index, d_Y, h_tau0, G, d_counts, "rr_rand_test");
+    if (s != RR_OK) return s;
+    Problem& P = p->P;
+    if ((s = ensure_aux(P, frt_scratch_bytes(P.n, K, G))) != RR_OK) return s;
+    return frt_run(P, seed, exact, d_keys, K, obs_index, d_Y, h_tau0, G, d_counts, h_tau_hat, (hipStream_t)stream,
+                   P.aux, "rr_rand_test");
+}
+
+extern "C" rr_status rr_rand_test_interval(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys,
+                                           uint64_t K, uint64_t obs_index, const double* d_Y, const double* h_tau0,
+                                           int64_t G, double alpha, uint64_t* d_counts, double* h_tau_hat,
+                                           double* h_interval, int* h_contiguous, void* stream) {
+    if (!(alpha > 0.0 && alpha < 1.0) || !h_interval || !h_contiguous || G < 1) {
+        set_error("rr_rand_test_interval: invalid argument");
         return RR_E_ARG;
     }
-    if (obs_index >= K) {
-        set_error("rr_rand_test: observed index not among the accepted keys");
-        return RR_E_OBS;
-    }
-    Problem& P = p->P;
-    if (exact && P.n > RR_MAX_N_EXACT) {
-        set_error("rr_rand_test: exact keys need n <= 64");
-        return RR_E_RANGE;
-    }
-    for (int64_t g = 0; g < G; ++g)
-        if (!std::isfinite(h_tau0[g])) {
-            set_error("rr_rand_test: tau0 must be finite");
-            return RR_E_ARG;
-        }
-    hipStream_t st = (hipStream_t)stream;
-    const int n = (int)P.n, n1 = (int)P.n1;
-    const int nw = (n + 31) / 32;
-    const uint64_t* binom = exact ? binom_table_ext(P.device) : nullptr;
-    int64_t *Yq = nullptr, *meta = nullptr, *alpha = nullptr, *beta = nullptr, *tm = nullptr;
-    int* tD = nullptr;
-    uint32_t* obits = nullptr;
-    uint64_t* okey = nullptr;
-    auto cleanup = [&]() {
-        hipFree(Yq);
-        hipFree(meta);
-        hipFree(alpha);
-        hipFree(beta);
-        hipFree(tm);
-        hipFree(tD);
-        hipFree(obits);
-    };
-#define RR_FHIP(call)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess) {                                                                \
-            set_error(std::string("rr_rand_test: ") + #call + ": " + hipGetErrorString(e_));    \
-            cleanup();                                                                         \
-            return RR_E_DEVICE;                                                                \
-        }                                                                                      \
-    } while (0)
-    RR_FHIP(hipMalloc(&Yq, sizeof(int64_t) * n));
-    RR_FHIP(hipMalloc(&meta, sizeof(int64_t) * 2));
-    RR_FHIP(hipMalloc(&alpha, sizeof(int64_t) * K));
-    RR_FHIP(hipMalloc(&beta, sizeof(int64_t) * K));
-    RR_FHIP(hipMalloc(&obits, sizeof(uint32_t) * nw));
-    RR_FHIP(hipMalloc(&tm, sizeof(int64_t) * std::max<int64_t>(G, 1)));
-    RR_FHIP(hipMalloc(&tD, sizeof(int) * std::max<int64_t>(G, 1)));
-    hipLaunchKernelGGL(frt_quantize_kernel, dim3(1), dim3(256), 0, st, d_Y, n, Yq, meta);
-    RR_FHIP(hipGetLastError());
-    // observed draw's bitmask
-    okey = const_cast<uint64_t*>(d_keys + obs_index);
-    if (exact)
-        RR_FHIP(launch_stats<true>(P.S, dim3(1), st, okey, 1, seed, n, n1, binom, Yq, meta, nullptr, nullptr,
-                                   nullptr, obits));
-    else
-        RR_FHIP(launch_stats<false>(P.S, dim3(1), st, okey, 1, seed, n, n1, binom, Yq, meta, nullptr, nullptr,
-                                    nullptr, obits));
-    const dim3 grid((unsigned)std::min<uint64_t>((K + 3) / 4, 4096));
-    if (exact)
-        RR_FHIP(launch_stats<true>(P.S, grid, st, d_keys, K, seed, n, n1, binom, Yq, meta, obits, alpha, beta,
-                                   nullptr));
-    else
-        RR_FHIP(launch_stats<false>(P.S, grid, st, d_keys, K, seed, n, n1, binom, Yq, meta, obits, alpha, beta,
-                                    nullptr));
-    int64_t hmeta[2];
-    int64_t halpha_o = 0;
-    RR_FHIP(hipMemcpyAsync(hmeta, meta, sizeof(hmeta), hipMemcpyDeviceToHost, st));
-    RR_FHIP(hipMemcpyAsync(&halpha_o, alpha + obs_index, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    RR_FHIP(hipStreamSynchronize(st));
-    const int s = (int)hmeta[0];
-    // tau0 = m 2^-E (m odd), D = s - E; range of the 128-bit comparison:
-    // |alpha| <= 2^62, |beta| <= n1 n0 <= n^2/4.
-    std::vector<int64_t> hm((size_t)std::max<int64_t>(G, 1));
-    std::vector<int> hD((size_t)std::max<int64_t>(G, 1));
-    const int bbits = bitlen_u((unsigned __int128)((uint64_t)n * (uint64_t)n / 4 + 1));
+    rr_status s = rr_rand_test(p, seed, exact, d_keys, K, obs_index, d_Y, h_tau0, G, d_counts, h_tau_hat, stream);
+    if (s != RR_OK) return s;
+    std::vector<uint64_t> c((size_t)G);
+    RR_HIP(hipMemcpyAsync(c.data(), d_counts, sizeof(uint64_t) * G, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    RR_HIP(hipStreamSynchronize((hipStream_t)stream));
+    // grid points whose p-value c_g / K exceeds alpha, in the caller's grid order
+    int64_t first = -1, last = -1, kept = 0;
+    double lo = NAN, hi = NAN;
     for (int64_t g = 0; g < G; ++g) {
-        const double t = h_tau0[g];
-        int64_t m = 0;
-        int D = 0;
-        if (t != 0.0) {
-            int e = 0;
-            const double f = std::frexp(t, &e);              // t = f 2^e, |f| in [0.5, 1)
-            int64_t mant = (int64_t)std::ldexp(f, 53);      // exact: t = mant 2^(e-53)
-            int E = 53 - e;
-            while ((mant & 1) == 0) {
-                mant /= 2;
-                --E;
-            }
-            m = mant;
-            D = s - E;
+        if ((double)c[g] / (double)K > alpha) {
+            if (first < 0) first = g;
+            last = g;
+            ++kept;
+            lo = std::isnan(lo) ? h_tau0[g] : std::min(lo, h_tau0[g]);
+            hi = std::isnan(hi) ? h_tau0[g] : std::max(hi, h_tau0[g]);
         }
-        const int mbits = bitlen_u((unsigned __int128)(m < 0 ? -m : m));
-        const bool ok = D >= 0 ? (mbits + D + bbits <= 125) : (62 - D <= 125 && mbits + bbits <= 125);
-        if (!ok) {
-            set_error("rr_rand_test: tau0 outside the exact comparison range");
-            cleanup();
-            return RR_E_RANGE;
-        }
-        hm[g] = m;
-        hD[g] = D;
     }
-    if (G > 0) {
-        RR_FHIP(hipMemcpyAsync(tm, hm.data(), sizeof(int64_t) * G, hipMemcpyHostToDevice, st));
-        RR_FHIP(hipMemcpyAsync(tD, hD.data(), sizeof(int) * G, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(frt_count_kernel, dim3((unsigned)G), dim3(256), 0, st, alpha, beta, K, obs_index, tm, tD,
-                           d_counts);
-        RR_FHIP(hipGetLastError());
-    }
-    RR_FHIP(hipStreamSynchronize(st));
-    if (h_tau_hat)
-        *h_tau_hat = std::ldexp((double)halpha_o, -s) / ((double)n1 * (double)(n - n1));
-    cleanup();
-#undef RR_FHIP
+    h_interval[0] = lo;
+    h_interval[1] = hi;
+    *h_contiguous = kept == 0 || kept == last - first + 1;
     return RR_OK;
 }

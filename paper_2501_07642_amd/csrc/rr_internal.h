@@ -54,6 +54,7 @@ __host__ __device__ inline uint32_t xcd_slot(uint32_t b, uint32_t g) {
 // Host-side description of a prepared problem.
 struct Problem {
     int device = 0;
+    uint64_t uid = 0;      // unique per prepared problem in this process (never reused)
     int64_t n = 0, d = 0, n1 = 0, n0 = 0;
     double ridge_rel = 0, lambda = 0;
     int metric = RR_METRIC_MAHALANOBIS;
@@ -81,11 +82,16 @@ struct Problem {
     // workspace for the draw pipeline (grown on demand)
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    // workspace of rr_balance_keys and rr_rand_test (grown on demand, kept with the handle)
+    void* aux = nullptr;
+    size_t aux_bytes = 0;
     hipStream_t gen_stream = nullptr;     // internal stream of the generation kernels
     std::vector<hipEvent_t> events;       // chunk ordering and timing
     struct BatchState* batch = nullptr;   // batched-call resources when this handle leads a batch
 };
 void free_batch_state(Problem& P);
+// Grows the handle's auxiliary workspace to at least `bytes` (device memory kept until rr_free).
+rr_status ensure_aux(Problem& P, size_t bytes);
 
 
 // ---------------------------------------------------------------------------------------

@@ -11,6 +11,7 @@
 // update of the trailing matrix); X~ by blocked forward substitution; BF16 hi/lo and FP32
 // operand records for the W X~ contraction; column sums of |X~| for the error bound.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -331,9 +332,13 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
         set_error("rr_prepare: n exceeds RR_MAX_N");
         return RR_E_UNSUPPORTED;
     }
+    int device = 0;
+    RR_HIP(hipGetDevice(&device));   // before the handle exists: nothing to release on failure
+    static std::atomic<uint64_t> next_uid{1};
     auto* h = new rr_problem();
     Problem& P = h->P;
-    RR_HIP(hipGetDevice(&P.device));
+    P.device = device;
+    P.uid = next_uid.fetch_add(1);
     P.n = n;
     P.d = d;
     P.n1 = n1;

@@ -358,6 +358,17 @@ static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint
     return RR_OK;
 }
 
+rr_status ensure_aux(Problem& P, size_t bytes) {
+    bytes = align256(std::max<size_t>(bytes, 256));
+    if (bytes <= P.aux_bytes) return RR_OK;
+    if (P.aux) RR_HIP(hipFree(P.aux));
+    P.aux = nullptr;
+    P.aux_bytes = 0;
+    RR_HIP(hipMalloc(&P.aux, bytes));
+    P.aux_bytes = bytes;
+    return RR_OK;
+}
+
 // ---------------------------------------------------------------------------------------
 // Error bound constants of the FP32 contraction.
 //
@@ -529,13 +540,17 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
     const uint32_t cand_cap = (uint32_t)std::max<uint64_t>(chunk + (1u << 20), 1u << 23);
     const uint32_t acc_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(capacity, 1), cand_cap);
     const uint32_t band_cap = 1u << 20;
-    WS w;
-    rr_status s = ensure_ws(P, cand_cap, acc_cap, band_cap, chunk * wpd, &w);
-    if (s != RR_OK) return s;
-    if ((s = ensure_streams(P, 4 * nchunks + 5)) != RR_OK) return s;
+    rr_status s = RR_OK;
     if (prec == RR_PREC_GRAM_BF16 && (s = ensure_gram(P, st)) != RR_OK) return s;
-    const Bound b = bound_constants(P, prec);
+    // The launch configuration is settled before any workspace pointer is taken: a first call
+    // of a tuning bucket probes candidates by running this pipeline on the same handle, and
+    // those runs may grow (reallocate) the workspace and the event list.
     const Tune tn = tune ? *tune : tune_for(P, prec, exact, N, st);
+    WS w;
+    if ((s = ensure_ws(P, cand_cap, acc_cap, band_cap, chunk * wpd, &w)) != RR_OK) return s;
+    if ((s = ensure_streams(P, 4 * nchunks + 5)) != RR_OK) return s;
+    const void* const ws_in_use = P.ws;
+    const Bound b = bound_constants(P, prec);
     const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
     if (exact && !binom) {
         set_error("rr_draw_exact: binomial table allocation failed");
@@ -603,6 +618,10 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         }
     }
     RR_HIP(hipStreamSynchronize(st));
+    if (P.ws != ws_in_use) {
+        set_error("rr_draw: workspace replaced during the call");
+        return RR_E_DEVICE;
+    }
     double contract_ms = 0, gen_ms = 0;
     for (uint64_t c = 0; c < nchunks; ++c) {
         float m1 = 0, m2 = 0;
@@ -726,6 +745,7 @@ void rr_free(rr_problem* p) {
     hipFree(P.op_gram);
     hipFree(P.cabs);
     hipFree(P.ws);
+    hipFree(P.aux);
     for (hipEvent_t e : P.events) hipEventDestroy(e);
     if (P.gen_stream) hipStreamDestroy(P.gen_stream);
     free_batch_state(P);
@@ -803,14 +823,17 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
     }
     hipStream_t st = (hipStream_t)stream;
     const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
+    // workspace: the count (first 256 bytes), then the bitmasks of the draws
+    const rr_status sa = ensure_aux(P, 256 + (d_M32 ? sizeof(uint32_t) * 8 * P.S * K : 0));
+    if (sa != RR_OK) return sa;
+    uint32_t* const cnt = (uint32_t*)P.aux;
+    uint32_t* const bits = (uint32_t*)((char*)P.aux + 256);
     if (d_M32) {
         if (precision == RR_PREC_GRAM_BF16) {
             const rr_status s = ensure_gram(P, st);
             if (s != RR_OK) return s;
         }
         const Bound b = bound_constants(P, precision);
-        uint32_t* bits = nullptr;
-        RR_HIP(hipMalloc(&bits, sizeof(uint32_t) * 8 * P.S * K));
         GenArgs g{};
         g.seed = seed;
         g.num = K;
@@ -830,14 +853,9 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
         a.out_err = d_err;
         const uint64_t tiles = (K + contract_tile(precision, P.S, 0) - 1) / contract_tile(precision, P.S, 0);
         if (e == hipSuccess) e = launch_contract(P.S, precision, 0, false, a, (int)std::min<uint64_t>(tiles, (uint64_t)cus), st);
-        hipError_t e2 = hipStreamSynchronize(st);
-        hipFree(bits);
         RR_HIP(e);
-        RR_HIP(e2);
     }
     if (d_M64) {
-        uint32_t* cnt = nullptr;
-        RR_HIP(hipMalloc(&cnt, sizeof(uint32_t)));
         const uint32_t k32 = (uint32_t)K;
         RR_HIP(hipMemcpyAsync(cnt, &k32, sizeof(k32), hipMemcpyHostToDevice, st));
         RecheckArgs ra{};
@@ -852,11 +870,7 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
         ra.d = (int)P.d;
         ra.scale = P.scale;
         ra.out = d_M64;
-        hipError_t e = launch_recheck(P.S, exact != 0, ra, (int)std::min<uint64_t>((K + 15) / 16, (uint64_t)device_cus(P.device) * 2), st);
-        hipError_t e2 = hipStreamSynchronize(st);
-        hipFree(cnt);
-        RR_HIP(e);
-        RR_HIP(e2);
+        RR_HIP(launch_recheck(P.S, exact != 0, ra, (int)std::min<uint64_t>((K + 15) / 16, (uint64_t)device_cus(P.device) * 2), st));
     }
     RR_HIP(hipStreamSynchronize(st));
     return RR_OK;

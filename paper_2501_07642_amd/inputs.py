@@ -78,6 +78,13 @@ WORKLOADS = {
         seed=0x5EED0006, key_begin=0, num_draws=100_000_000, mode="quantile", q=1e-4,
         precision="gram_bf16", tau=0.5, noise_sd=1.0, y_seed=602,
         taus=list(np.linspace(-2.0, 2.0, 201)), obs_seed=603),
+    # a small streaming pool of more than 16 chunks of 2^20 draws whose keys cross 2^32: the
+    # running acceptance bound is refreshed twice while streaming (a parity case, not a bench line)
+    "refresh_n64_d8": dict(
+        kind="mc", n=64, n1=32, d=8, x="gaussian", x_seed=701, ridge_rel=0.0,
+        seed=0x5EED0007, key_begin=(1 << 32) - 3_000_000, num_draws=16 * (1 << 20) + (1 << 19) + 77,
+        mode="quantile", q=1e-4, precision="split_bf16", tau=0.5, noise_sd=1.0, y_seed=702,
+        taus=list(np.linspace(-2.0, 2.0, 21)), obs_seed=703),
     "batched_512": dict(
         kind="batched", num_problems=512, shape_seed=501, x_seed_base=10_000,
         ridge_rel=1e-2, seed_base=0x5EED0500, key_begin=0, num_draws=100_000,

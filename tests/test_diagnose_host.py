@@ -79,3 +79,21 @@ def test_errors(rr):
         rr.rr_diagnose(5, 5, 3, 0.1, 1.0, 1.0)
     with pytest.raises(rr.RRError):
         rr.rr_q_star(5, 5, 3, 1.0, 0.5, 0.0)
+
+
+def test_realized_rmse_matches_oracle(rr):
+    """Appendix A part A: typical-orientation RMSE and Cauchy-Schwarz bound of a realised M
+    (library on the chi^2 scale, oracle on the paper's scale (1/n1 + 1/n0) M)."""
+    for n1, n0, d, M, sigma, r2 in [(500, 500, 1000, 866.0, 1.0, 0.4), (10, 30, 3, 0.05, 2.0, 0.9),
+                                    (50, 70, 20, 0.0, 0.5, 0.0), (7, 7, 1, 3.2, 1.0, 0.5)]:
+        t, b = rr.rr_realized_rmse(n1, n0, d, M, sigma, r2)
+        mp = (1.0 / n1 + 1.0 / n0) * M
+        assert abs(t - diagnose.rmse_typical(sigma, r2, d, mp, n1, n0)) <= 1e-13 * t
+        assert abs(b - diagnose.rmse_bound(sigma, r2, mp, n1, n0)) <= 1e-13 * b
+        assert t <= b
+    # at d = 1 the typical orientation is the bound (one direction only)
+    t, b = rr.rr_realized_rmse(7, 9, 1, 2.5, 1.0, 0.3)
+    assert abs(t - b) <= 1e-15 * b
+    for args in [(5, 5, 3, -1.0), (5, 5, 3, float("nan")), (0, 5, 3, 1.0)]:
+        with pytest.raises(rr.RRError):
+            rr.rr_realized_rmse(*args)
