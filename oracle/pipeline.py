@@ -29,7 +29,10 @@ def balance_of_keys(X, n1, ridge_rel, seed, keys, exact=False, batch=10000, metr
             W = np.stack([assign.exact_assignment(int(r), n, n1) for r in kb])
         else:
             W = assign.mc_assignments_batch(seed, kb, n, n1)
-        out[s:s + batch] = balance.mahalanobis_batch(X, W, P["S_lam"])
+        if metric == "max_smd":
+            out[s:s + batch] = balance.max_smd_batch(X, W, np.diag(P["S_lam"]))
+        else:
+            out[s:s + batch] = balance.mahalanobis_batch(X, W, P["S_lam"])
     return out
 
 

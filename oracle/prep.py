@@ -19,6 +19,8 @@ whitened case.  The readings implemented here:
   (section 2.2 writes M for standardised covariates; a diagonal approximation is also one
   reading of ``approximate_inv``).  A variance below 1e-10 times the largest one is
   reported as singular.
+* metric = "max_smd": the same standardisation, for the per-column criterion (the largest
+  squared standardised mean difference instead of their sum, see ``balance``).
 """
 
 import numpy as np
@@ -42,12 +44,12 @@ def prepare(X, n1, ridge_rel=0.0, metric="mahalanobis"):
     """Return dict(mu, S, lam, S_lam, L) for covariates X (n x d)."""
     X = np.asarray(X, dtype=np.float64)
     n, d = X.shape
-    if not (1 <= n1 <= n - 1) or d < 1 or ridge_rel < 0 or metric not in ("mahalanobis", "diagonal"):
+    if not (1 <= n1 <= n - 1) or d < 1 or ridge_rel < 0 or metric not in ("mahalanobis", "diagonal", "max_smd"):
         raise ValueError("bad arguments")
     mu, S = covariance(X)
     lam = ridge_rel * np.trace(S) / d
     S_lam = S + lam * np.eye(d)
-    if metric == "diagonal":
+    if metric in ("diagonal", "max_smd"):
         S_lam = np.diag(np.diag(S_lam))
     try:
         L = np.linalg.cholesky(S_lam)

@@ -152,3 +152,59 @@ def test_diagonal_constant_column_is_singular():
     X[:, 1] = 2.0
     with pytest.raises(prep.SingularCovariance):
         prep.prepare(X, 5, 0.0, "diagonal")
+
+
+# ---- per-column criterion: the largest squared standardised mean difference
+def all_M_max(X, n1, ridge_rel=0.0):
+    P = prep.prepare(X, n1, ridge_rel, "max_smd")
+    W = assign.exact_assignments(X.shape[0], n1)
+    return W, balance.max_smd_batch(X, W, np.diag(P["S_lam"])), P
+
+
+def test_max_smd_one_covariate_is_the_two_sample_statistic():
+    # with d = 1 the largest term is the only term: the textbook two-sample z^2 (Mahalanobis),
+    # with and without a ridge
+    X = np.random.default_rng(30).standard_normal((12, 1)) * 3.0 + 1.0
+    for ridge in (0.0, 0.4):
+        _, Mx, _ = all_M_max(X, 5, ridge)
+        _, Mm, _ = all_M_metric(X, 5, "mahalanobis", ridge)
+        np.testing.assert_allclose(Mx, Mm, rtol=1e-12)
+
+
+def test_max_smd_between_max_and_sum():
+    # max_j z_j^2 <= sum_j z_j^2 <= d max_j z_j^2 for every assignment, and the sum is the
+    # standardise-only M
+    X = np.random.default_rng(31).standard_normal((12, 4)) @ np.random.default_rng(32).standard_normal((4, 4))
+    W, Mx, _ = all_M_max(X, 6)
+    _, Md, _ = all_M_metric(X, 6, "diagonal")
+    assert np.all(Mx <= Md * (1 + 1e-12)) and np.all(Md <= 4 * Mx * (1 + 1e-12))
+    # and each column alone gives a lower bound that is attained by the largest column
+    per_col = np.stack([all_M_metric(X[:, [j]], 6, "diagonal")[1] for j in range(4)])
+    np.testing.assert_allclose(Mx, per_col.max(axis=0), rtol=1e-12)
+
+
+def test_max_smd_duplicated_and_rescaled_columns():
+    # a column repeated with another scale and offset changes nothing (per-column
+    # standardisation); permuting the columns changes nothing; M(w) = M(1 - w)
+    X = np.random.default_rng(33).standard_normal((11, 3))
+    W, Mx, _ = all_M_max(X, 4)
+    X2 = np.column_stack([X[:, 2], X[:, 0] * -7.0 + 3.0, X[:, 1], X[:, 0] * 0.01])
+    _, Mx2, _ = all_M_max(X2, 4)
+    np.testing.assert_allclose(Mx2, Mx, rtol=1e-10)
+    P = prep.prepare(X, 5, 0.0, "max_smd")
+    W5 = assign.exact_assignments(11, 5)
+    W6 = 1 - W5
+    np.testing.assert_allclose(balance.max_smd_batch(X, W5, np.diag(P["S_lam"])),
+                               balance.max_smd_batch(X, W6, np.diag(P["S_lam"])), rtol=1e-12)
+
+
+def test_max_smd_distribution_is_max_of_chi2_1():
+    # independent Gaussian columns: M_max ~ max of d chi^2_1, P(M_max <= t) = F_1(t)^d
+    n, d, N = 2000, 5, 3000
+    X = np.random.default_rng(34).standard_normal((n, d))
+    P = prep.prepare(X, n // 2, 0.0, "max_smd")
+    W = assign.mc_assignments_batch(19, np.arange(N, dtype=np.uint64), n, n // 2)
+    Mx = balance.max_smd_batch(X, W, np.diag(P["S_lam"]))
+    assert stats.kstest(Mx, lambda t: stats.chi2(1).cdf(t) ** d).pvalue > 1e-3
+    # the sum of the terms would follow chi^2_d instead: clearly rejected
+    assert stats.kstest(Mx, stats.chi2(d).cdf).pvalue < 1e-6
