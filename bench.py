@@ -61,23 +61,42 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(X, w, sample):
-    """The oracle, as it stands, on the first `sample` draws of the workload."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(X, w, sample, sample_1t):
+    """The oracle, as it stands, on the first `sample` draws of the workload with the host's
+    BLAS threads, and on the first `sample_1t` draws with one thread."""
     import numpy as np
     from oracle import accept, pipeline
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = len(os.sched_getaffinity(0))
-    keys = np.arange(sample, dtype=np.uint64)
-    t0 = time.perf_counter()
-    M = pipeline.balance_of_keys(X, w["n1"], w["ridge_rel"], w["seed"], keys, metric=w.get("metric", "mahalanobis"))
-    accept.accept_quantile(keys, M, accept.quantile_count(w["q"], sample))
-    dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "draws/s", "cores": int(cores), "kind": "oracle",
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    def run(count):
+        keys = np.arange(count, dtype=np.uint64)
+        t0 = time.perf_counter()
+        M = pipeline.balance_of_keys(X, w["n1"], w["ridge_rel"], w["seed"], keys,
+                                     metric=w.get("metric", "mahalanobis"))
+        accept.accept_quantile(keys, M, accept.quantile_count(w["q"], count))
+        return count / (time.perf_counter() - t0), time.perf_counter() - t0
+
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    rate, dt = run(sample)
+    with threadpool_limits(1):
+        rate1, dt1 = run(sample_1t)
+    return {"value": rate, "unit": "draws/s", "cores": int(threads), "kind": "oracle",
             "sample": f"first {sample} draw keys of the workload: Philox draws, n1-of-n selection, "
-                      f"FP64 textbook M, q-quantile acceptance over the sample ({dt:.1f} s)"}
+                      f"FP64 textbook M, q-quantile acceptance over the sample ({dt:.1f} s; BLAS on {threads} "
+                      f"threads, the oracle's NumPy element-wise steps on one)",
+            "cpu_model": cpu_model(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "one_thread": {"value": rate1, "unit": "draws/s", "cores": 1,
+                           "sample": f"first {sample_1t} draw keys ({dt1:.1f} s)"}}
 
 
 def run_batched(args, rr, inputs, np, torch):
@@ -174,6 +193,7 @@ def main():
     ap.add_argument("--workload", default="stream_n1000_d1000")
     ap.add_argument("--draws", type=int, default=None, help="override the draw count (not the benchmark)")
     ap.add_argument("--cpu-sample", type=int, default=200000)
+    ap.add_argument("--cpu-sample-1t", type=int, default=20000, help="draws of the one-thread oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-i8", action="store_true", help="skip the fixed-point int8 comparison leg")
@@ -253,16 +273,24 @@ def main():
     value = N / (ms_per_step / 1000.0)
     keys_split = keys_s.cpu().numpy()
 
-    # hi and lo products of the dense W X~ contraction (the Gram form: W K, K = X~ X~^T n x n)
-    flops_per_draw = 4.0 * n * (n if gram else d)
+    # Algorithmic work of one balance check (the method, not the dense form): the treated sum
+    # G = sum_{i in T} X~_i is n1 d additions, and ||G||^2 is d multiply-adds.  The dense form
+    # issues the hi and lo products of W X~ over all n units (the Gram form: W K, K n x n).
+    alg_flops_per_draw = float(n1 * d + 2 * d)
+    issued_per_draw = 4.0 * n * (n if gram else d)
+    launches_per_step = launches / args.steps
     avg_launch_ms = contract_ms / max(launches, 1)
-    achieved = flops_per_draw * N * args.steps / (contract_ms / 1000.0) / 1e12
+    achieved = alg_flops_per_draw * N * args.steps / (contract_ms / 1000.0) / 1e12
+    issued = issued_per_draw * N * args.steps / (contract_ms / 1000.0) / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None if gram else measured_traffic(),
                 "kernel": ("contract_kernel<Gram BF16> (W K on 32x32x16 BF16 MFMA + w^T (W K) + prefilter)" if gram else
                            "contract_kernel<split BF16> (W X~ on 32x32x16 BF16 MFMA + reduce + prefilter)"),
-                "avg_launch_ms": avg_launch_ms, "launches_per_step": launches / args.steps,
-                "algorithmic_flops_per_draw": flops_per_draw,
+                "avg_launch_ms": avg_launch_ms, "launches_per_step": launches_per_step,
+                "draws_per_launch": N / max(launches_per_step, 1),
+                "algorithmic_flops_per_draw": alg_flops_per_draw,
+                "issued_mfma_flops_per_draw": issued_per_draw, "issued_mfma_tflops": issued,
+                "issued_mfma_frac": issued / PEAK_BF16_TFLOPS,
                 "gen_kernel_ms_per_step": gen_ms / args.steps}
 
     split = None
@@ -307,18 +335,20 @@ def main():
             g8 += t["gen_ms"]
         torch.cuda.synchronize()
         ms8 = 1000.0 * (time.perf_counter() - t1) / args.steps
-        a8 = flops_per_draw * N * args.steps / (c8 / 1000.0) / 1e12
+        a8 = issued_per_draw * N * args.steps / (c8 / 1000.0) / 1e12
+        g8_alg = alg_flops_per_draw * N * args.steps / (c8 / 1000.0) / 1e12
         i8 = {"draws_per_s": N / (ms8 / 1000.0), "ms_per_step": ms8, "contract_kernel_ms_per_step": c8 / args.steps,
               "gen_kernel_ms_per_step": g8 / args.steps,
               "same_accept_set": bool(np.array_equal(keys8.cpu().numpy(), keys_split)),
-              "mfma_tops": a8, "frac_int8_peak": a8 / PEAK_INT8_TOPS, "guard_band": t["band"],
+              "algorithmic_tops": g8_alg, "algorithmic_frac_int8_peak": g8_alg / PEAK_INT8_TOPS,
+              "issued_mfma_tops": a8, "issued_frac_int8_peak": a8 / PEAK_INT8_TOPS, "guard_band": t["band"],
               "speedup_vs_split": ms_per_step / ms8,
               "kernel": "contract_kernel<fixed I8> (x = s (128 hi + lo), 32x32x32 int8 MFMA, exact int32)",
-              "algorithmic_ops_per_draw": flops_per_draw}
+              "algorithmic_ops_per_draw": alg_flops_per_draw, "issued_ops_per_draw": issued_per_draw}
 
     base = None
     if not args.no_cpu_baseline:
-        base = cpu_baseline(X, w, args.cpu_sample)
+        base = cpu_baseline(X, w, args.cpu_sample, args.cpu_sample_1t)
 
     out = {
         "metric": METRIC_GRAM if gram else METRIC, "value": value, "unit": "draws/s", "n_gpus": 1, "steps": args.steps,

@@ -52,7 +52,7 @@ typedef enum {
 enum { RR_MODE_QUANTILE = 0, RR_MODE_THRESHOLD = 1, RR_MODE_CHI2_QUANTILE = 2 };
 enum { RR_PREC_SPLIT_BF16 = 0, RR_PREC_FP32 = 1, RR_PREC_FIXED_I8 = 2, RR_PREC_GRAM_BF16 = 3 };
 enum { RR_X_FP64 = 0, RR_X_FP32 = 1 };
-enum { RR_METRIC_MAHALANOBIS = 0, RR_METRIC_DIAGONAL = 1 };
+enum { RR_METRIC_MAHALANOBIS = 0, RR_METRIC_DIAGONAL = 1, RR_METRIC_MAX_SMD = 2 };
 
 /* Largest unit count of a Monte Carlo problem in this build. */
 #define RR_MAX_N 4096
@@ -86,6 +86,12 @@ rr_status rr_prepare(const void* d_X, int x_dtype, int64_t n, int64_t d, int64_t
  *            S_lam is replaced by its diagonal, so M = (n1 n0 / n) sum_j Delta_j^2 /
  *            (S_jj + lambda), the sum of squared standardised mean differences (section 2.2
  *            states M for standardised covariates).  Every later call is unchanged.
+ *   metric = RR_METRIC_MAX_SMD: the per-column criterion: the same standardisation, and the
+ *            balance value of a draw is the largest squared standardised mean difference,
+ *            M = (n1 n0 / n) max_j Delta_j^2 / (S_jj + lambda) (section 2.2 writes M as the sum
+ *            of the squared SMD_j; this scores the worst covariate instead, on the chi^2_1 scale
+ *            of each term).  Acceptance, outputs and the guard band work on this value; the
+ *            Gram form has no per-column sums and is rejected with it (RR_E_ARG).
  * Errors as rr_prepare (RR_E_SINGULAR: some S_jj + lambda <= 1e-10 max S_jj); RR_E_ARG for an
  * unknown metric.
  */

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 MODE_QUANTILE, MODE_THRESHOLD, MODE_CHI2_QUANTILE = 0, 1, 2
 PREC_SPLIT_BF16, PREC_FP32, PREC_FIXED_I8, PREC_GRAM_BF16 = 0, 1, 2, 3
 X_FP64, X_FP32 = 0, 1
-METRIC_MAHALANOBIS, METRIC_DIAGONAL = 0, 1
+METRIC_MAHALANOBIS, METRIC_DIAGONAL, METRIC_MAX_SMD = 0, 1, 2
 STATUS = {0: "RR_OK", 1: "RR_E_ARG", 2: "RR_E_SINGULAR", 3: "RR_E_CAPACITY", 4: "RR_E_RANGE",
           5: "RR_E_OBS", 6: "RR_E_DEVICE", 7: "RR_E_UNSUPPORTED"}
 

@@ -296,6 +296,10 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     const int cus = device_cus(dev);
     if (precision == RR_PREC_GRAM_BF16) {
         for (int64_t i = 0; i < nprob; ++i) {
+            if (P[i]->P.metric == RR_METRIC_MAX_SMD) {
+                set_error("rr_draw_balance_batched: the Gram form has no per-column sums (RR_METRIC_MAX_SMD)");
+                return RR_E_ARG;
+            }
             const rr_status s = ensure_gram(P[i]->P, st);
             if (s != RR_OK) return s;
         }
@@ -463,6 +467,7 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             ra.n1 = (int)Q.n1;
             ra.d = (int)Q.d;
             ra.scale = Q.scale;
+            ra.maxmode = Q.metric == RR_METRIC_MAX_SMD ? 1 : 0;
             ra.out = d_bm + boff[i];
             rt[gpos[gi] + j] = ra;
             // small d: the draws accepted outright are recomputed in FP64 as well (cap 0 skips)

@@ -13,7 +13,8 @@
 // the B operand (16 units x 32 draws of W^T) is expanded from the tile's bitmasks in LDS.
 // In an output block, lane l holds draw l % 32 and 16 covariates, so ||G||^2 is reduced in
 // registers and across the two lane halves; the error bounds need only ||G|| (or, for the
-// Gram form, the sum of |G'_j| over the treated units).
+// Gram form, the sum of |G'_j| over the treated units).  For the per-column criterion
+// (maxmode) the same reduction takes the largest G_j^2 instead of the sum.
 //
 //   split BF16: X~ = hi + lo, two 32x32x16 BF16 MFMA per K step into one FP32 accumulator;
 //   FP32:       32x32x2 FP32 MFMA; each K step starts from zero and is added on the VALU;
@@ -280,19 +281,34 @@ void contract_kernel(ContractArgs a0) {
                         } else if constexpr (PREC == RR_PREC_FIXED_I8) {
                             // G = s I, I the exact int32 sums of this block
                             float t = 0.f;
-#pragma unroll
-                            for (int r = 0; r < 16; ++r) {
-                                const float g = (float)acc[cb][db][r];
-                                t = fmaf(g, g, t);
-                            }
                             const float sc = a.bscale[chunk * CB + cb];
-                            s2 = fmaf(sc * sc, t, s2);
-                        } else {
+                            if (a.maxmode) {
 #pragma unroll
-                            for (int r = 0; r < 16; ++r) s2 = fmaf(acc[cb][db][r], acc[cb][db][r], s2);
+                                for (int r = 0; r < 16; ++r) {
+                                    const float g = (float)acc[cb][db][r];
+                                    t = fmaxf(t, g * g);
+                                }
+                                s2 = fmaxf(s2, (sc * sc) * t);
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < 16; ++r) {
+                                    const float g = (float)acc[cb][db][r];
+                                    t = fmaf(g, g, t);
+                                }
+                                s2 = fmaf(sc * sc, t, s2);
+                            }
+                        } else {
+                            if (a.maxmode) {
+#pragma unroll
+                                for (int r = 0; r < 16; ++r) s2 = fmaxf(s2, acc[cb][db][r] * acc[cb][db][r]);
+                            } else {
+#pragma unroll
+                                for (int r = 0; r < 16; ++r) s2 = fmaf(acc[cb][db][r], acc[cb][db][r], s2);
+                            }
                         }
                     }
-                    ss[db] += s2;
+                    // per-column criterion: the largest G_j^2 instead of the sum
+                    ss[db] = (!kGram && a.maxmode) ? fmaxf(ss[db], s2) : ss[db] + s2;
                     if constexpr (kGram) ssa[db] += sa;
                 }
             }
@@ -303,7 +319,8 @@ void contract_kernel(ContractArgs a0) {
 #pragma unroll
         for (int db = 0; db < DB; ++db) {
             // the split form summed (2G)^2, the Gram form 2 G' (W enters as 2.0)
-            const float s2 = (ss[db] + __shfl_xor(ss[db], 32, 64)) *
+            const float other = __shfl_xor(ss[db], 32, 64);
+            const float s2 = ((!kGram && a.maxmode) ? fmaxf(ss[db], other) : ss[db] + other) *
                              (PREC == RR_PREC_SPLIT_BF16 ? 0.25f : (kGram ? 0.5f : 1.0f));
             const uint64_t idx = tile0 + wave * 32 * DB + 32 * db + j;
             const bool live = h == 0 && idx < a.num;

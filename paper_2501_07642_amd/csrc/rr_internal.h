@@ -79,6 +79,8 @@ struct Problem {
     double gram_ctop = 0;      // sum of the n1 largest column sums of |K| (host, error bound)
     float* cabs = nullptr;     // 32 * ncb column sums of |X~| (rounded up; 0 for pads)
     double cabs_c2 = 0;        // sum of cabs^2 (host copy, for the error bound)
+    double cabs_max = 0;       // max of cabs (host copy, bound of the per-column criterion)
+    double qerr_max = 0;       // max_j e_j of the fixed-point form (host)
     // workspace for the draw pipeline (grown on demand)
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -119,6 +121,7 @@ struct ContractArgs {
     float cnorm;              // ||cabs||_2, rounded up
     float gamma_ss;           // relative bound of the FP32 sum of squares and the scaling
     float safety;             // multiplies the assembled bound
+    int maxmode;              // 1: M = scale max_j G_j^2 (per-column criterion), else scale sum_j G_j^2
     const float* U;           // append iff lo <= *U; null appends every draw
     uint64_t* cand_key;
     float* cand_hi;
@@ -145,6 +148,7 @@ struct RecheckArgs {
     int n, n1, d;
     double scale;
     double* out;              // M64 per entry
+    int maxmode;              // 1: M = scale max_j G_j^2, else scale sum_j G_j^2
 };
 
 // Up to this many covariates every accepted draw is reported with its FP64 M: the BF16
@@ -217,6 +221,13 @@ hipError_t launch_recheck_batch(int S, const RecheckArgs* tab, int nprob, uint32
 int pow2_chunks(int n);
 int device_cus(int dev);
 const uint64_t* binom_table(int dev);
+const uint64_t* binom_table_ready(int dev);
+// M32 / error bound / M64 of given draws, enqueued on `st` with caller-provided scratch: `cnt`
+// (one uint32) and `bits` (8 S words per draw when d_M32 is set).
+rr_status balance_keys_enqueue(Problem& P, uint64_t seed, bool exact, const uint64_t* binom,
+                               const uint64_t* d_keys, uint64_t K, int precision, float* d_M32,
+                               float* d_err, double* d_M64, uint32_t* cnt, uint32_t* bits,
+                               hipStream_t st);
 Bound bound_constants(const Problem& P, int prec);
 ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b);
 Tune tune_default(int prec, int S, bool batch);

@@ -324,7 +324,7 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
                        double ridge_rel, int metric, hipStream_t st, rr_problem** out) {
     if (!dX || !out || n < 2 || d < 1 || ldx < d || n1 < 1 || n1 > n - 1 || !(ridge_rel >= 0.0) ||
         (x_dtype != RR_X_FP64 && x_dtype != RR_X_FP32) ||
-        (metric != RR_METRIC_MAHALANOBIS && metric != RR_METRIC_DIAGONAL)) {
+        (metric != RR_METRIC_MAHALANOBIS && metric != RR_METRIC_DIAGONAL && metric != RR_METRIC_MAX_SMD)) {
         set_error("rr_prepare: invalid argument");
         return RR_E_ARG;
     }
@@ -395,7 +395,7 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     RR_PHIP(gemm_nt(st, d, d, n, 1.0 / (double)(n - 1), P.X64, 1, d, P.X64, 1, d, 0.0, A, d));
     hipLaunchKernelGGL(ridge_kernel, dim3(1), dim3(256), 0, st, A, d, ridge_rel, scal);
     RR_PHIP(hipGetLastError());
-    if (metric == RR_METRIC_DIAGONAL) {
+    if (metric != RR_METRIC_MAHALANOBIS) {
         hipLaunchKernelGGL(diag_factor_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, A, d, piv, bad);
         RR_PHIP(hipGetLastError());
     }
@@ -458,18 +458,33 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
         RR_PHIP(hipMemcpyAsync(hc.data(), P.cabs, sizeof(float) * dpad, hipMemcpyDeviceToHost, st));
         RR_PHIP(hipMemcpyAsync(he.data(), qe, sizeof(double) * d, hipMemcpyDeviceToHost, st));
         RR_PHIP(hipStreamSynchronize(st));
-        double c2 = 0.0;
-        for (float c : hc) c2 += (double)c * (double)c;
+        double c2 = 0.0, cmax = 0.0;
+        for (float c : hc) {
+            c2 += (double)c * (double)c;
+            cmax = std::max(cmax, (double)c);
+        }
         P.cabs_c2 = c2;
-        double e2 = 0.0;
-        for (double e : he) e2 += e * e;
+        P.cabs_max = cmax;
+        double e2 = 0.0, emax = 0.0;
+        for (double e : he) {
+            e2 += e * e;
+            emax = std::max(emax, e);
+        }
         P.qerr_c2 = e2 * (1.0 + 1e-12);
+        P.qerr_max = emax;
     }
     hipFree(qe);
     hipFree(S);
     hipFree(piv);
     hipFree(scal);
     hipFree(bad);
+    qe = S = piv = scal = nullptr;
+    bad = nullptr;
+    // the device's binomial table (exact-mode keys), so that later calls find it without allocating
+    if (!binom_table(device)) {
+        set_error("rr_prepare: binomial table allocation failed");
+        return fail(RR_E_DEVICE);
+    }
 #undef RR_PHIP
     *out = h;
     return RR_OK;

@@ -1,7 +1,7 @@
 // FP64 recomputation of M for draws in the guard band (and for rr_balance_keys).
 //
 // M = n / (n1 n0) ||G||^2 with G = sum_{i in T} X~_i (section 2.2; Appendix A remark), in
-// FP64 on the whitened covariates.  Exactly representable 0/1 weights make the FP64 matrix
+// FP64 on the whitened covariates; for the per-column criterion n / (n1 n0) max_j G_j^2.  Exactly representable 0/1 weights make the FP64 matrix
 // product W X~ the same sums, accumulated with FP64 roundings.
 #include <algorithm>
 
@@ -98,7 +98,9 @@ __device__ __forceinline__ void recheck_cols(const RecheckArgs& a, const uint32_
         for (int q = 0; q < G; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                if (cval[j]) part[q][r] = fma(acc[j][q][r], acc[j][q][r], part[q][r]);
+                if (cval[j])
+                    part[q][r] = a.maxmode ? fmax(part[q][r], acc[j][q][r] * acc[j][q][r])
+                                           : fma(acc[j][q][r], acc[j][q][r], part[q][r]);
 }
 
 // Entries e0 .. min(e0 + 16 G, cnt) - 1 of the list (workgroup-uniform arguments).
@@ -160,14 +162,17 @@ __device__ __forceinline__ void recheck_tile(const RecheckArgs& a, uint32_t e0, 
             for (int r = 0; r < 4; ++r) {
                 double v = part[q][r];
 #pragma unroll
-                for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+                for (int o = 8; o >= 1; o >>= 1) {
+                    const double u = __shfl_xor(v, o, 64);
+                    v = a.maxmode ? fmax(v, u) : v + u;
+                }
                 if (c == 0) sh.red[wave * kRecheckTile + 16 * q + 4 * r + g] = v;
             }
         __syncthreads();
         if (tid < nt) {
             double v = sh.red[tid];
 #pragma unroll
-            for (int w = 1; w < NW; ++w) v += sh.red[w * kRecheckTile + tid];
+            for (int w = 1; w < NW; ++w) v = a.maxmode ? fmax(v, sh.red[w * kRecheckTile + tid]) : v + sh.red[w * kRecheckTile + tid];
             a.out[e0 + tid] = a.scale * v;
         }
         __syncthreads();
