@@ -183,6 +183,26 @@ rr_status rr_balance_keys(rr_problem* p, uint64_t seed, int exact, const uint64_
                           double* d_M64, void* stream);
 
 /*
+ * rr_balance_keys_noalloc -- rr_balance_keys for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, outputs and results as rr_balance_keys, but:
+ *   - its scratch is a fixed 64 MiB array in the library's device memory (one per GPU, held
+ *     until the process ends) instead of the handle's workspace, so it calls no hipMalloc /
+ *     hipFree / allocating routine; K is limited to (2^26 - 256) / (32 S) keys when d_M32 is
+ *     set (S = ceil(n/256) rounded up to a power of two: 524286 keys at n <= 1024), else
+ *     RR_E_UNSUPPORTED with the limit in rr_last_error();
+ *   - it only enqueues kernels on `stream` and returns without synchronising: outputs are
+ *     ready once the stream has reached that point;
+ *   - every call on a GPU shares that GPU's scratch array: calls that overlap on one GPU (on
+ *     different streams or threads) race and must be ordered by the caller;
+ *   - the current device must be the handle's (RR_E_ARG otherwise), and RR_PREC_GRAM_BF16
+ *     needs the handle's Gram operands built by an earlier allocating call (RR_E_ARG).
+ */
+rr_status rr_balance_keys_noalloc(rr_problem* p, uint64_t seed, int exact, const uint64_t* d_keys,
+                                  uint64_t K, int precision, float* d_M32, float* d_err,
+                                  double* d_M64, void* stream);
+
+/*
  * rr_rand_test -- randomization test conditioned on acceptance (section 2.3
  * randomization_test; section 4 "Design-based inference").
  *

@@ -28,6 +28,7 @@ SIGNATURES = [
     ("rr_draw_exact", _I, [_P, _I, _D, _I, _P, _P, _P, _U64, C.POINTER(_U64), _P]),
     ("rr_regenerate", _I, [_P, _U64, _I, _P, _U64, _P, _P]),
     ("rr_balance_keys", _I, [_P, _U64, _I, _P, _U64, _I, _P, _P, _P, _P]),
+    ("rr_balance_keys_noalloc", _I, [_P, _U64, _I, _P, _U64, _I, _P, _P, _P, _P]),
     ("rr_rand_test", _I, [_P, _U64, _I, _P, _U64, _U64, _P, _P, _I64, _P, C.POINTER(_D), _P]),
     ("rr_rand_test_interval", _I, [_P, _U64, _I, _P, _U64, _U64, _P, _P, _I64, _D, _P, C.POINTER(_D), _P,
                                    C.POINTER(_I), _P]),
@@ -206,6 +207,15 @@ def rr_balance_keys(P, seed, keys, precision=PREC_SPLIT_BF16, exact=False, want_
     m64 = torch.empty(K, dtype=torch.float64, device=keys.device) if want_m64 else None
     _check(load().rr_balance_keys(P.handle, seed, int(exact), _ptr(keys), K, precision, _ptr(m32), _ptr(err),
                                   _ptr(m64), _stream()))
+    return m32, err, m64
+
+
+def rr_balance_keys_noalloc(P, seed, keys, m32, err, m64, precision=PREC_SPLIT_BF16, exact=False):
+    """The allocation-free variant: the caller passes the output tensors (or None); the call only
+    enqueues work on torch's current stream."""
+    keys = keys.contiguous()
+    _check(load().rr_balance_keys_noalloc(P.handle, seed, int(exact), _ptr(keys), keys.numel(), precision,
+                                          _ptr(m32), _ptr(err), _ptr(m64), _stream()))
     return m32, err, m64
 
 

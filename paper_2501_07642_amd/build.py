@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librr.so")
 ARCH = os.environ.get("RR_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["rr_prep.hip", "rr_gen.hip", "rr_contract.hip", "rr_recheck.hip", "rr_select.hip", "rr_frt.hip",
-           "rr_tune.hip", "rr_batch.hip", "rr_diagnose.cpp"]
+           "rr_tune.hip", "rr_batch.hip", "rr_noalloc.hip", "rr_diagnose.cpp"]
 
 
 def hipcc():
