@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-from oracle import assign, balance, pipeline, prep  # noqa: E402
+from oracle import assign, balance, frt, pipeline, prep  # noqa: E402
 from paper_2501_07642_amd import inputs  # noqa: E402
 
 
@@ -302,3 +302,67 @@ def test_pool_extreme_n1(rr, prec):
     for n1 in (1, 96):
         say(f"pool n=97 n1={n1} {prec}")
         _check_pool(rr, X, n1, 0.0, 31, 3000, "quantile", 0.02, prec)
+
+
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8", "gram"])
+@pytest.mark.parametrize("n,d", [(50, 1), (500, 2), (257, 1)])
+def test_pool_one_and_two_covariates(rr, prec, n, d):
+    """d = 1 and 2: M is a single (or a sum of two) squared standardised difference(s); small
+    values, one column block padded with 31 (or 30) zero columns."""
+    say(f"pool n={n} d={d} {prec}")
+    X = inputs.gaussian_X(n, d, 40 + n + d)
+    _, got, t = _check_pool(rr, X, n // 2, 0.0, 777 + d, 30_000, "quantile", 0.004, prec)
+    say(f"  accepted {len(got)} band {t['band']}")
+
+
+def test_rand_test_interval_c2(rr):
+    """Inversion of the test over the null grid: [min, max] of the grid values whose p-value
+    exceeds alpha, and whether they are contiguous in the caller's grid order."""
+    name = "mc_n100_d100"
+    w = inputs.WORKLOADS[name]
+    say("C2 fiducial interval")
+    X = inputs.workload_X(name)
+    P = rr.rr_prepare(dev(X), w["n1"], w["ridge_rel"])
+    keys, _, _ = rr.rr_draw_balance(P, w["seed"], 0, 20_000, rr.MODE_QUANTILE, w["q"], rr.PREC_SPLIT_BF16)
+    acc = u64(keys)
+    obs = inputs.obs_pick(len(acc), w["obs_seed"])
+    wo = pipeline.regenerate(w["seed"], acc[obs:obs + 1], w["n"], w["n1"])[0]
+    Y = inputs.outcomes(X, wo, w["tau"], w["noise_sd"], w["y_seed"])
+    taus = list(w["taus"])
+    ref = pipeline.rand_test_keys(w["seed"], acc, w["n"], w["n1"], obs, Y, taus)
+    K = len(acc)
+    for alpha in (0.05, 0.2):
+        counts, tau_hat, (lo, hi), contig = rr.rr_rand_test_interval(P, w["seed"], keys, obs, dev(Y), taus, alpha)
+        assert counts.cpu().tolist() == ref["counts"]
+        iv = frt.interval(taus, [c / K for c in ref["counts"]], alpha)
+        assert (lo, hi, contig) == (iv["lo"], iv["hi"], iv["contiguous"]), (lo, hi, contig, iv)
+        say(f"  alpha {alpha}: [{lo}, {hi}] contiguous {contig}, tau_hat {tau_hat:.3f}")
+    # the same grid in a shuffled order: the kept values are no longer contiguous in that order
+    perm = np.random.default_rng(3).permutation(len(taus))
+    shuffled = [taus[i] for i in perm]
+    counts, _, (lo, hi), contig = rr.rr_rand_test_interval(P, w["seed"], keys, obs, dev(Y), shuffled, 0.05)
+    iv = frt.interval(shuffled, [ref["counts"][i] / K for i in perm], 0.05)
+    assert (lo, hi, contig) == (iv["lo"], iv["hi"], iv["contiguous"]) and contig is False
+    # no grid value kept: both ends NaN, reported contiguous
+    far = [10.0, 11.0, -12.5]
+    _, _, (lo, hi), contig = rr.rr_rand_test_interval(P, w["seed"], keys, obs, dev(Y), far, 0.05)
+    assert math.isnan(lo) and math.isnan(hi) and contig
+    with pytest.raises(rr.RRError):
+        rr.rr_rand_test_interval(P, w["seed"], keys, obs, dev(Y), taus, 1.0)
+
+
+def test_rand_test_range_edges(rr):
+    """Null values at the edges of the always-accepted range (|tau0| = 2^-8, just below 2^20)
+    and their negatives: counts equal the oracle's exact rational counts."""
+    say("FRT range edges")
+    X = inputs.gaussian_X(80, 5, 9)
+    P = rr.rr_prepare(dev(X), 40, 0.0)
+    keys, _, _ = rr.rr_draw_balance(P, 21, 0, 40_000, rr.MODE_QUANTILE, 0.01, rr.PREC_SPLIT_BF16)
+    acc = u64(keys)
+    wo = pipeline.regenerate(21, acc[7:8], 80, 40)[0]
+    Y = inputs.outcomes(X, wo, 0.3, 1.0, 10)
+    edge = math.nextafter(2.0 ** 20, 0.0)
+    taus = [2.0 ** -8, -2.0 ** -8, math.nextafter(2.0 ** -8, 1.0), edge, -edge, 0.0, 1e5 + 0.125]
+    counts, _ = rr.rr_rand_test(P, 21, keys, 7, dev(Y), taus)
+    ref = pipeline.rand_test_keys(21, acc, 80, 40, 7, Y, taus)
+    assert counts.cpu().tolist() == ref["counts"]
