@@ -16,7 +16,8 @@
  *     named h_* are host pointers.  The caller owns all of them.
  *   - `stream` is a hipStream_t passed as void* (0 = the null stream).  Calls enqueue their
  *     kernels on it and return after the work has completed (they synchronise the stream
- *     when a data-dependent size must be known on the host), so outputs are ready on return.
+ *     when a data-dependent size must be known on the host), so outputs are ready on return;
+ *     the exceptions, rr_draw_balance_async and rr_balance_keys_noalloc, only enqueue.
  *   - On any error nothing is written to the outputs, except RR_E_CAPACITY, which writes
  *     the required count to *h_count.  rr_last_error() returns a message for the last
  *     failing call of the calling thread.
@@ -150,6 +151,29 @@ rr_status rr_draw_balance(rr_problem* p, uint64_t seed, uint64_t key_begin,
                           uint64_t num_draws, int mode, double q_or_a, int precision,
                           uint64_t* d_keys, double* d_M, uint8_t* d_flags,
                           uint64_t capacity, uint64_t* h_count, void* stream);
+
+/*
+ * rr_draw_balance_async -- rr_draw_balance, stream-ordered: the call enqueues all its work on
+ * `stream` (and on the handle's internal generation stream, joined to it by events) and
+ * returns without waiting.  The accepted count and the status are written on the device:
+ *   d_count   device, 1 uint64: the accepted count K (on RR_E_CAPACITY, the required count);
+ *   d_status  device, 1 int32: RR_OK, or the rr_status the synchronous call would have
+ *             returned for a condition detected on the device (RR_E_CAPACITY,
+ *             RR_E_UNSUPPORTED for a candidate or guard-band list beyond its capacity,
+ *             RR_E_DEVICE for an inconsistent selection).
+ * Results are identical to rr_draw_balance; on a device-detected error nothing is written to
+ * d_keys / d_M / d_flags.  Arguments checked on the host are returned as usual (with
+ * RR_E_CAPACITY for q N above the capacity, the count is also written to d_count).  The
+ * caller synchronises `stream` before reading any output.  Differences: the autotuner is not
+ * run (its cached choice or the default tile is used), rr_last_timing is not updated, and a
+ * call that must grow the handle's workspace, or build the Gram operands, waits for the work
+ * in flight first.  Successive calls on one handle and stream are ordered by the stream.
+ */
+rr_status rr_draw_balance_async(rr_problem* p, uint64_t seed, uint64_t key_begin,
+                                uint64_t num_draws, int mode, double q_or_a, int precision,
+                                uint64_t* d_keys, double* d_M, uint8_t* d_flags,
+                                uint64_t capacity, uint64_t* d_count, int32_t* d_status,
+                                void* stream);
 
 /*
  * rr_draw_exact -- exact enumeration (section 2.3, randomization_type = "exact"): every

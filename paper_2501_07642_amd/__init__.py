@@ -10,7 +10,7 @@ from . import _lib  # noqa: F401
 from ._lib import (  # noqa: F401
     METRIC_DIAGONAL, METRIC_MAHALANOBIS, METRIC_MAX_SMD, MODE_CHI2_QUANTILE, MODE_QUANTILE, MODE_THRESHOLD, PREC_FIXED_I8, PREC_FP32, PREC_GRAM_BF16, PREC_SPLIT_BF16,
     RRError, Problem,
-    lib_path, load, rr_balance_keys, rr_balance_keys_noalloc, rr_draw_balance, rr_draw_balance_batched,
+    lib_path, load, rr_balance_keys, rr_balance_keys_noalloc, rr_draw_balance, rr_draw_balance_async, rr_draw_balance_batched,
     rr_diagnose, rr_draw_exact, rr_last_timing, rr_prepare, rr_q_star, rr_rand_test, rr_rand_test_interval,
     rr_realized_rmse,
     rr_regenerate, quantile_count,

@@ -25,6 +25,7 @@ SIGNATURES = [
     ("rr_problem_n1", _I64, [_P]),
     ("rr_problem_lambda", _D, [_P]),
     ("rr_draw_balance", _I, [_P, _U64, _U64, _U64, _I, _D, _I, _P, _P, _P, _U64, C.POINTER(_U64), _P]),
+    ("rr_draw_balance_async", _I, [_P, _U64, _U64, _U64, _I, _D, _I, _P, _P, _P, _U64, _P, _P, _P]),
     ("rr_draw_exact", _I, [_P, _I, _D, _I, _P, _P, _P, _U64, C.POINTER(_U64), _P]),
     ("rr_regenerate", _I, [_P, _U64, _I, _P, _U64, _P, _P]),
     ("rr_balance_keys", _I, [_P, _U64, _I, _P, _U64, _I, _P, _P, _P, _P]),
@@ -173,6 +174,23 @@ def rr_draw_balance(P, seed, key_begin, num_draws, mode=MODE_QUANTILE, q_or_a=0.
     _check(st, cnt.value)
     k = cnt.value
     return keys[:k], M[:k], flags[:k]
+
+
+def rr_draw_balance_async(P, seed, key_begin, num_draws, mode=MODE_QUANTILE, q_or_a=0.01,
+                          precision=PREC_SPLIT_BF16, capacity=None, out=None):
+    """Enqueues the pool on torch's current stream and returns (keys, M, flags, count, status) device
+    tensors without waiting; count (int64 [1]) and status (int32 [1]) are written on the device.
+    `out` may pass (keys, M, flags) tensors to fill instead of fresh ones."""
+    torch = _torch()
+    if capacity is None:
+        capacity = quantile_count(q_or_a, num_draws) if mode == MODE_QUANTILE else num_draws
+    keys, M, flags = out if out is not None else _draw_outputs(max(capacity, 1), P.device)
+    count = torch.zeros(1, dtype=torch.int64, device=P.device)
+    status = torch.full((1,), -1, dtype=torch.int32, device=P.device)
+    _check(load().rr_draw_balance_async(P.handle, seed, key_begin, num_draws, mode, float(q_or_a), precision,
+                                        _ptr(keys), _ptr(M), _ptr(flags), capacity, _ptr(count), _ptr(status),
+                                        _stream()))
+    return keys, M, flags, count, status
 
 
 def rr_draw_exact(P, mode=MODE_QUANTILE, q_or_a=0.01, precision=PREC_SPLIT_BF16, capacity=None):

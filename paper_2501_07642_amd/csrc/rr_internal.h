@@ -231,13 +231,16 @@ rr_status balance_keys_enqueue(Problem& P, uint64_t seed, bool exact, const uint
 Bound bound_constants(const Problem& P, int prec);
 ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b);
 Tune tune_default(int prec, int S, bool batch);
-Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t st);
+// probe = false: the cached choice or the default, never a timed probe (asynchronous calls).
+Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t st, bool probe = true);
 rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begin, uint64_t N, int mode,
                         double q_or_a, int prec, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
-                        uint64_t capacity, uint64_t* h_count, hipStream_t st, const Tune* tune);
+                        uint64_t capacity, uint64_t* h_count, hipStream_t st, const Tune* tune,
+                        uint64_t* d_count = nullptr, int32_t* d_status = nullptr);
 hipError_t sort_accepted(const uint64_t* acc_key, const double* acc_m, const uint8_t* acc_flag, uint32_t n,
                          uint64_t* const sk[2], uint32_t* const si[2], uint64_t* out_key, double* out_m,
-                         uint8_t* out_flag, hipStream_t st);
+                         uint8_t* out_flag, hipStream_t st, const uint32_t* n_dev = nullptr,
+                         const int32_t* status = nullptr);
 double chi2_quantile_of(double q, double d);   // q-quantile of chi^2_d (inf for q = 1)
 void set_timing(double total_ms, double contract_ms, double gen_ms, int64_t launches, uint64_t band);
 }  // namespace rr

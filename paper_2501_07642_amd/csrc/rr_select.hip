@@ -109,11 +109,12 @@ static bool binom_exact(int64_t n, int64_t k, uint64_t* out) {
 // ---------------------------------------------------------------------------------------
 // Kernels: radix selection of the k-th smallest of two float arrays (bit patterns of
 // non-negative floats order like the values), one 8-bit digit per pass.
-__global__ void sel_hist_kernel(const float* a0, const float* a1, const uint32_t* count, Ctl* ctl, int shift) {
+__global__ void sel_hist_kernel(const float* a0, const float* a1, const uint32_t* count, uint32_t cap, Ctl* ctl,
+                                int shift) {
     __shared__ uint32_t h[2][256];
     for (int i = threadIdx.x; i < 512; i += blockDim.x) (&h[0][0])[i] = 0;
     __syncthreads();
-    const uint32_t n = *count;
+    const uint32_t n = min(*count, cap);   // appends past the capacity were not stored
     const uint32_t m = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
     const uint32_t p0 = ctl->sel_prefix[0] & m, p1 = ctl->sel_prefix[1] & m;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -167,8 +168,8 @@ __global__ void update_U_kernel(Ctl* ctl) {
 __global__ void classify_kernel(const uint64_t* ck, const float* chi, const float* clo, const float* cm,
                                 Ctl* ctl, int mode, double a, uint64_t* acc_key, double* acc_m,
                                 uint8_t* acc_flag, uint32_t acc_cap, uint64_t* band_key,
-                                uint32_t band_cap) {
-    const uint32_t n = ctl->cand_count;
+                                uint32_t band_cap, uint32_t cand_cap) {
+    const uint32_t n = min(ctl->cand_count, cand_cap);
     double lo_cut = 0.0, hi_cut = 0.0;
     if (mode == RR_MODE_QUANTILE) {
         lo_cut = (double)__uint_as_float(ctl->sel_prefix[1]) * (1.0 - kEpsTie);
@@ -194,6 +195,35 @@ __global__ void classify_kernel(const uint64_t* ck, const float* chi, const floa
 
 // flag[i] = 1 for i < min(*count, cap)
 __global__ void set_count_kernel(uint32_t* c, uint32_t v) { *c = v; }
+__global__ void set_count64_kernel(uint64_t* c, uint64_t v) { *c = v; }
+
+// The control block of a call: zeroed, then the accepted count k and the prefilter bound U
+// (a kernel rather than a memset and a host copy, so that a call only enqueues kernels).
+__global__ __launch_bounds__(256) void init_ctl_kernel(Ctl* ctl, uint32_t k, float U) {
+    uint32_t* words = reinterpret_cast<uint32_t*>(ctl);
+    for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / sizeof(uint32_t); i += blockDim.x) words[i] = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->ac.k = k;
+        ctl->U = U;
+    }
+}
+
+// Status and count of an asynchronous call, decided on the device from the control block:
+// the same checks the synchronous call makes on the host, in the same order.
+__global__ void async_status_kernel(const Ctl* ctl, uint32_t cand_cap, uint64_t capacity, int quantile, uint32_t k,
+                                    uint64_t* d_count, int32_t* d_status) {
+    int32_t st = RR_OK;
+    const uint64_t K = ctl->ac.acc_count;
+    if (ctl->cand_count > cand_cap) st = RR_E_UNSUPPORTED;
+    else if (ctl->sel_fail || ctl->ac.guard_fail) st = RR_E_DEVICE;
+    else if (ctl->overflow) st = RR_E_UNSUPPORTED;
+    else if (K > capacity) st = RR_E_CAPACITY;
+    else if (quantile && K != k) st = RR_E_DEVICE;
+    // RR_E_CAPACITY reports the required count; other errors write no count
+    if (st == RR_OK || st == RR_E_CAPACITY) *d_count = K;
+    *d_status = st;
+}
 
 __global__ void fill_flags_kernel(uint8_t* flag, const uint32_t* count, uint32_t cap) {
     const uint32_t n = min(*count, cap);
@@ -221,11 +251,18 @@ __global__ __launch_bounds__(1024) void band_accept_kernel(const uint64_t* bkey,
 // partner run (keys are distinct).
 constexpr int kSortChunk = 2048;
 
-__global__ __launch_bounds__(1024) void sort_chunk_kernel(const uint64_t* key, uint32_t n, uint64_t* okey,
-                                                          uint32_t* oidx) {
+// n_dev (when set) bounds n on the device: a launch sized for n covers a count known only there.
+__device__ __forceinline__ uint32_t sort_count(uint32_t n, const uint32_t* n_dev) {
+    return n_dev ? min(n, *n_dev) : n;
+}
+
+__global__ __launch_bounds__(1024) void sort_chunk_kernel(const uint64_t* key, uint32_t n_max, const uint32_t* n_dev,
+                                                          uint64_t* okey, uint32_t* oidx) {
     __shared__ uint64_t sk[kSortChunk];
     __shared__ uint32_t si[kSortChunk];
+    const uint32_t n = sort_count(n_max, n_dev);
     const uint32_t base = blockIdx.x * kSortChunk;
+    if (base >= n) return;   // workgroup-uniform
     for (int i = threadIdx.x; i < kSortChunk; i += blockDim.x) {
         const uint32_t g = base + i;
         sk[i] = g < n ? key[g] : ~0ull;
@@ -242,8 +279,11 @@ __global__ __launch_bounds__(1024) void sort_chunk_kernel(const uint64_t* key, u
     }
 }
 
-__global__ void merge_pass_kernel(const uint64_t* ik, const uint32_t* ii, uint32_t n, uint32_t width,
-                                  uint64_t* ok, uint32_t* oi) {
+// A pass whose width is at least n copies its input unchanged (every element is in run A and
+// run B is empty), so the ping-pong buffer of the result does not depend on the device count.
+__global__ void merge_pass_kernel(const uint64_t* ik, const uint32_t* ii, uint32_t n_max, const uint32_t* n_dev,
+                                  uint32_t width, uint64_t* ok, uint32_t* oi) {
+    const uint32_t n = sort_count(n_max, n_dev);
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const uint32_t pair = g / (2 * width);
@@ -272,31 +312,35 @@ __global__ void merge_pass_kernel(const uint64_t* ik, const uint32_t* ii, uint32
     oi[pos] = ii[g];
 }
 
-__global__ void gather_out_kernel(const uint64_t* sk, const uint32_t* si, uint32_t n, const double* m,
-                                  const uint8_t* f, uint64_t* okey, double* om, uint8_t* of) {
+// Writes nothing unless the call's status (when given) is RR_OK.
+__global__ void gather_out_kernel(const uint64_t* sk, const uint32_t* si, uint32_t n_max, const uint32_t* n_dev,
+                                  const int32_t* status, const double* m, const uint8_t* f, uint64_t* okey,
+                                  double* om, uint8_t* of) {
+    const uint32_t n = sort_count(n_max, n_dev);
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
+    if (g >= n || (status && *status != RR_OK)) return;
     okey[g] = sk[g];
     om[g] = m[si[g]];
     if (of && f) of[g] = f[si[g]];
 }
 
 // Accepted (key, M, flag) triples sorted by key into the outputs; sk / si are two scratch
-// buffers of n entries each.
+// buffers of n entries each.  With n_dev set, n is an upper bound and the count is read on
+// the device (asynchronous calls), and `status` gates the output writes.
 hipError_t sort_accepted(const uint64_t* acc_key, const double* acc_m, const uint8_t* acc_flag, uint32_t n,
                          uint64_t* const sk[2], uint32_t* const si[2], uint64_t* out_key, double* out_m,
-                         uint8_t* out_flag, hipStream_t st) {
+                         uint8_t* out_flag, hipStream_t st, const uint32_t* n_dev, const int32_t* status) {
     if (n == 0) return hipSuccess;
     const uint32_t chunks = (n + kSortChunk - 1) / kSortChunk;
-    hipLaunchKernelGGL(sort_chunk_kernel, dim3(chunks), dim3(1024), 0, st, acc_key, n, sk[0], si[0]);
+    hipLaunchKernelGGL(sort_chunk_kernel, dim3(chunks), dim3(1024), 0, st, acc_key, n, n_dev, sk[0], si[0]);
     int cur = 0;
     for (uint32_t width = kSortChunk; width < n; width *= 2) {
-        hipLaunchKernelGGL(merge_pass_kernel, dim3((n + 255) / 256), dim3(256), 0, st, sk[cur], si[cur], n, width,
-                           sk[cur ^ 1], si[cur ^ 1]);
+        hipLaunchKernelGGL(merge_pass_kernel, dim3((n + 255) / 256), dim3(256), 0, st, sk[cur], si[cur], n, n_dev,
+                           width, sk[cur ^ 1], si[cur ^ 1]);
         cur ^= 1;
     }
-    hipLaunchKernelGGL(gather_out_kernel, dim3((n + 255) / 256), dim3(256), 0, st, sk[cur], si[cur], n, acc_m,
-                       acc_flag, out_key, out_m, out_flag);
+    hipLaunchKernelGGL(gather_out_kernel, dim3((n + 255) / 256), dim3(256), 0, st, sk[cur], si[cur], n, n_dev, status,
+                       acc_m, acc_flag, out_key, out_m, out_flag);
     return hipGetLastError();
 }
 
@@ -338,6 +382,8 @@ static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint
                  o_i1 = take(4ull * acc_cap);
     const size_t o_b0 = take(4ull * bits_words), o_b1 = take(4ull * bits_words);
     if (off > P.ws_bytes) {
+        // an asynchronous call on this handle may still be using the old workspace
+        if (P.ws) RR_HIP(hipDeviceSynchronize());
         if (P.ws) hipFree(P.ws);
         P.ws = nullptr;
         P.ws_bytes = 0;
@@ -371,6 +417,7 @@ static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint
 rr_status ensure_aux(Problem& P, size_t bytes) {
     bytes = align256(std::max<size_t>(bytes, 256));
     if (bytes <= P.aux_bytes) return RR_OK;
+    if (P.aux) RR_HIP(hipDeviceSynchronize());
     if (P.aux) RR_HIP(hipFree(P.aux));
     P.aux = nullptr;
     P.aux_bytes = 0;
@@ -508,7 +555,7 @@ static hipError_t run_select(WS& w, hipStream_t st) {
     hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(1), 0, st, w.ctl);
     for (int shift = 24; shift >= 0; shift -= 8) {
         hipLaunchKernelGGL(sel_hist_kernel, dim3(512), dim3(256), 0, st, w.cand_hi, w.cand_lo,
-                           &w.ctl->cand_count, w.ctl, shift);
+                           &w.ctl->cand_count, w.cand_cap, w.ctl, shift);
         hipLaunchKernelGGL(sel_scan_kernel, dim3(1), dim3(128), 0, st, w.ctl, shift);
     }
     return hipGetLastError();
@@ -517,7 +564,11 @@ static hipError_t run_select(WS& w, hipStream_t st) {
 // The draw pipeline shared by Monte Carlo and exact enumeration.
 rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begin, uint64_t N, int mode,
                         double q_or_a, int prec, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
-                        uint64_t capacity, uint64_t* h_count, hipStream_t st, const Tune* tune) {
+                        uint64_t capacity, uint64_t* h_count, hipStream_t st, const Tune* tune,
+                        uint64_t* d_count, int32_t* d_status) {
+    // Asynchronous calls (d_status set) only enqueue: every size the host would otherwise read
+    // back is bounded from above, and the checks run on the device into d_status / d_count.
+    const bool async = d_status != nullptr;
     auto t_start = std::chrono::steady_clock::now();
     if (mode == RR_MODE_CHI2_QUANTILE) {
         // a fixed threshold from the chi-square approximation of M
@@ -528,8 +579,8 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         q_or_a = chi2_quantile_of(q_or_a, (double)P.d);
         mode = RR_MODE_THRESHOLD;
     }
-    if (N == 0 || !d_keys || !d_M || !h_count || (mode != RR_MODE_QUANTILE && mode != RR_MODE_THRESHOLD) ||
-        !valid_prec(prec)) {
+    if (N == 0 || !d_keys || !d_M || (async ? !d_count : !h_count) ||
+        (mode != RR_MODE_QUANTILE && mode != RR_MODE_THRESHOLD) || !valid_prec(prec)) {
         set_error("rr_draw: invalid argument");
         return RR_E_ARG;
     }
@@ -546,7 +597,12 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         k = (uint64_t)std::ceil(q_or_a * (double)N * (1.0 - kQFuzz));
         k = std::min<uint64_t>(std::max<uint64_t>(k, 1), N);
         if (k > capacity) {
-            *h_count = k;
+            if (async) {
+                hipLaunchKernelGGL(set_count64_kernel, dim3(1), dim3(1), 0, st, d_count, k);
+                RR_HIP(hipGetLastError());
+            } else {
+                *h_count = k;
+            }
             set_error("rr_draw: capacity below the accepted count");
             return RR_E_CAPACITY;
         }
@@ -572,7 +628,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
     // The launch configuration is settled before any workspace pointer is taken: a first call
     // of a tuning bucket probes candidates by running this pipeline on the same handle, and
     // those runs may grow (reallocate) the workspace and the event list.
-    const Tune tn = tune ? *tune : tune_for(P, prec, exact, N, st);
+    const Tune tn = tune ? *tune : tune_for(P, prec, exact, N, st, !async);
     WS w;
     if ((s = ensure_ws(P, cand_cap, acc_cap, band_cap, chunk * wpd, &w)) != RR_OK) return s;
     if ((s = ensure_streams(P, 4 * nchunks + 5)) != RR_OK) return s;
@@ -584,17 +640,14 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         return RR_E_DEVICE;
     }
 
-    RR_HIP(hipMemsetAsync(w.ctl, 0, sizeof(Ctl), st));
     {
-        Ctl init{};
-        init.ac.k = (uint32_t)k;
-        init.U = INFINITY;
+        float U = INFINITY;
         if (mode == RR_MODE_THRESHOLD) {
-            float u = (float)q_or_a;
-            if ((double)u < q_or_a) u = std::nextafter(u, INFINITY);
-            init.U = u;
+            U = (float)q_or_a;
+            if ((double)U < q_or_a) U = std::nextafter(U, INFINITY);
         }
-        RR_HIP(hipMemcpyAsync(w.ctl, &init, offsetof(Ctl, hist), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(init_ctl_kernel, dim3(1), dim3(256), 0, st, w.ctl, (uint32_t)k, U);
+        RR_HIP(hipGetLastError());
     }
     hipEvent_t* ev = P.events.data();
     hipEvent_t ev_start = ev[0], *ev_ready = ev + 1, *ev_free = ev + 3;
@@ -644,34 +697,37 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
             RR_HIP(hipGetLastError());
         }
     }
-    RR_HIP(hipStreamSynchronize(st));
     if (P.ws != ws_in_use) {
         set_error("rr_draw: workspace replaced during the call");
         return RR_E_DEVICE;
     }
     double contract_ms = 0, gen_ms = 0;
-    for (uint64_t c = 0; c < nchunks; ++c) {
-        float m1 = 0, m2 = 0;
-        RR_HIP(hipEventElapsedTime(&m1, ev_t[4 * c], ev_t[4 * c + 1]));
-        RR_HIP(hipEventElapsedTime(&m2, ev_t[4 * c + 2], ev_t[4 * c + 3]));
-        contract_ms += m1;
-        gen_ms += m2;
+    Ctl hc{};
+    if (!async) {
+        RR_HIP(hipStreamSynchronize(st));
+        for (uint64_t c = 0; c < nchunks; ++c) {
+            float m1 = 0, m2 = 0;
+            RR_HIP(hipEventElapsedTime(&m1, ev_t[4 * c], ev_t[4 * c + 1]));
+            RR_HIP(hipEventElapsedTime(&m2, ev_t[4 * c + 2], ev_t[4 * c + 3]));
+            contract_ms += m1;
+            gen_ms += m2;
+        }
+        RR_HIP(hipMemcpyAsync(&hc, w.ctl, offsetof(Ctl, hist), hipMemcpyDeviceToHost, st));
+        RR_HIP(hipStreamSynchronize(st));
+        if (hc.cand_count > cand_cap) {
+            set_error("rr_draw: candidate buffer overflow (too many draws near the boundary)");
+            return RR_E_UNSUPPORTED;
+        }
     }
     const int64_t launches = (int64_t)nchunks;
-    Ctl hc;
-    RR_HIP(hipMemcpyAsync(&hc, w.ctl, offsetof(Ctl, hist), hipMemcpyDeviceToHost, st));
-    RR_HIP(hipStreamSynchronize(st));
-    if (hc.cand_count > cand_cap) {
-        set_error("rr_draw: candidate buffer overflow (too many draws near the boundary)");
-        return RR_E_UNSUPPORTED;
-    }
+    // grids: from the candidate count when it is known on the host, else persistent
+    const uint32_t nc = async ? cand_cap : hc.cand_count;
     if (mode == RR_MODE_QUANTILE) RR_HIP(run_select(w, st));
     {
-        const uint32_t nc = hc.cand_count;
         const int grid = (int)std::max<uint32_t>(1, std::min<uint32_t>((nc + 255) / 256, 4096));
         hipLaunchKernelGGL(classify_kernel, dim3(grid), dim3(256), 0, st, w.cand_key, w.cand_hi, w.cand_lo,
                            w.cand_m, w.ctl, mode, q_or_a, w.acc_key, w.acc_m, w.acc_flag, acc_cap, w.band_key,
-                           band_cap);
+                           band_cap, cand_cap);
         RR_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(cap_band_kernel, dim3(1), dim3(1), 0, st, w.ctl, band_cap);
@@ -688,7 +744,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
     ra.scale = P.scale;
     ra.maxmode = P.metric == RR_METRIC_MAX_SMD ? 1 : 0;
     ra.out = w.band_m;
-    RR_HIP(launch_recheck(P.S, exact, ra, (int)std::min<uint64_t>((hc.cand_count + 15) / 16 + 1, (uint64_t)device_cus(P.device) * 2), st));
+    RR_HIP(launch_recheck(P.S, exact, ra, (int)std::min<uint64_t>((nc + 15) / 16 + 1, (uint64_t)cus * 2), st));
     if (refine_accepted(P, prec)) {
         // the draws accepted outright are reported with their FP64 values too
         RecheckArgs rf = ra;
@@ -696,14 +752,25 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         rf.count = &w.ctl->ac.acc_count;
         rf.cap = acc_cap;
         rf.out = w.acc_m;
-        RR_HIP(launch_recheck(P.S, exact, rf, (int)std::min<uint64_t>((std::min<uint64_t>(hc.cand_count, acc_cap) + 15) / 16 + 1,
-                                                                      (uint64_t)device_cus(P.device) * 2), st));
+        RR_HIP(launch_recheck(P.S, exact, rf, (int)std::min<uint64_t>((std::min<uint64_t>(nc, acc_cap) + 15) / 16 + 1,
+                                                                      (uint64_t)cus * 2), st));
         hipLaunchKernelGGL(fill_flags_kernel, dim3(64), dim3(256), 0, st, w.acc_flag, &w.ctl->ac.acc_count, acc_cap);
         RR_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(band_accept_kernel, dim3(1), dim3(1024), 0, st, w.band_key, w.band_m, w.band_work, w.ctl,
                        mode, q_or_a, w.acc_key, w.acc_m, w.acc_flag, acc_cap);
     RR_HIP(hipGetLastError());
+    if (async) {
+        // status and count on the device; the sort covers the largest count that can be
+        // written (k, or the capacity) and reads the actual one there
+        hipLaunchKernelGGL(async_status_kernel, dim3(1), dim3(1), 0, st, w.ctl, cand_cap, capacity,
+                           mode == RR_MODE_QUANTILE ? 1 : 0, (uint32_t)k, d_count, d_status);
+        RR_HIP(hipGetLastError());
+        const uint32_t n_max = mode == RR_MODE_QUANTILE ? (uint32_t)k : acc_cap;
+        RR_HIP(sort_accepted(w.acc_key, w.acc_m, w.acc_flag, n_max, w.sk, w.si, d_keys, d_M, d_flags, st,
+                             &w.ctl->ac.acc_count, d_status));
+        return RR_OK;
+    }
     RR_HIP(hipMemcpyAsync(&hc, w.ctl, offsetof(Ctl, hist), hipMemcpyDeviceToHost, st));
     RR_HIP(hipStreamSynchronize(st));
     if (hc.sel_fail || hc.ac.guard_fail) {
@@ -814,6 +881,7 @@ rr_status rr_prepare_metric(const void* d_X, int x_dtype, int64_t n, int64_t d, 
 void rr_free(rr_problem* p) {
     if (!p) return;
     Problem& P = p->P;
+    hipDeviceSynchronize();   // asynchronous calls on this handle may still be running
     hipFree(P.X64);
     hipFree(P.L);
     hipFree(P.mu);
@@ -849,6 +917,21 @@ rr_status rr_draw_balance(rr_problem* p, uint64_t seed, uint64_t key_begin, uint
     }
     return draw_pipeline(p->P, false, seed, key_begin, num_draws, mode, q_or_a, precision, d_keys, d_M, d_flags,
                          capacity, h_count, (hipStream_t)stream, nullptr);
+}
+
+rr_status rr_draw_balance_async(rr_problem* p, uint64_t seed, uint64_t key_begin, uint64_t num_draws, int mode,
+                                double q_or_a, int precision, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
+                                uint64_t capacity, uint64_t* d_count, int32_t* d_status, void* stream) {
+    if (!p || !d_status) {
+        set_error("rr_draw_balance_async: null handle or status pointer");
+        return RR_E_ARG;
+    }
+    if (key_begin + num_draws < key_begin) {
+        set_error("rr_draw_balance_async: key range wraps");
+        return RR_E_ARG;
+    }
+    return draw_pipeline(p->P, false, seed, key_begin, num_draws, mode, q_or_a, precision, d_keys, d_M, d_flags,
+                         capacity, nullptr, (hipStream_t)stream, nullptr, d_count, d_status);
 }
 
 rr_status rr_draw_exact(rr_problem* p, int mode, double q_or_a, int precision, uint64_t* d_keys, double* d_M,

@@ -118,7 +118,7 @@ void save_file() {
 
 }  // namespace
 
-Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t st) {
+Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t st, bool probe) {
     const Tune def = tune_default(prec, P.S, false);
     if (exact || !tuning_enabled()) return def;
     std::lock_guard<std::mutex> g(g_mu);
@@ -131,7 +131,7 @@ Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t
         t.gen_wg = std::min(t.gen_wg, gen_wg_fit(prec, P.S, t.db, false));
         return t;
     }
-    if (work_draws < (1u << 20)) return def;
+    if (work_draws < (1u << 20) || !probe) return def;
 
     // probe pool: ~2^42 MFMA flops, 2^18 .. 2^20 draws
     const double ncb = (double)(prec == RR_PREC_GRAM_BF16 ? P.ncb_gram : P.ncb);
