@@ -80,6 +80,9 @@ struct Problem {
     float* cabs = nullptr;     // 32 * ncb column sums of |X~| (rounded up; 0 for pads)
     double cabs_c2 = 0;        // sum of cabs^2 (host copy, for the error bound)
     double cabs_max = 0;       // max of cabs (host copy, bound of the per-column criterion)
+    // bounds e_j of |G32_j - G_j| over the covariates (host): sum of squares and largest, for
+    // the split BF16 and FP32 contractions
+    double esplit_n2 = 0, esplit_max = 0, ef32_n2 = 0, ef32_max = 0;
     double qerr_max = 0;       // max_j e_j of the fixed-point form (host)
     // workspace for the draw pipeline (grown on demand)
     void* ws = nullptr;
@@ -229,6 +232,11 @@ rr_status balance_keys_enqueue(Problem& P, uint64_t seed, bool exact, const uint
                                float* d_err, double* d_M64, uint32_t* cnt, uint32_t* bits,
                                hipStream_t st);
 Bound bound_constants(const Problem& P, int prec);
+// Bounds of |G32_j - G_j| for column j from the per-column sums of the preparation: the
+// step-weighted sum of |X~|, the sum of the per-half maxima and the representation residual
+// (split), and sum |X~|, the step-weighted sum and the residual (FP32).
+double split_column_bound(const Problem& P, double wsum_j, double halfmax_j, double resid_j);
+double fp32_column_bound(const Problem& P, double cabs_j, double wsum_j, double resid_j);
 ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b);
 Tune tune_default(int prec, int S, bool batch);
 // probe = false: the cached choice or the default, never a timed probe (asynchronous calls).

@@ -11,6 +11,7 @@
 // update of the trailing matrix); X~ by blocked forward substitution; BF16 hi/lo and FP32
 // operand records for the W X~ contraction; column sums of |X~| for the error bound.
 #include <algorithm>
+#include <tuple>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -309,6 +310,53 @@ __global__ void cabs_kernel(const double* X, int64_t n, int64_t d, int64_t dpad,
     cabs[j] = f;
 }
 
+// Per-column quantities behind the error bounds of the FP32 contractions (out[5 d]: five
+// arrays of d, each sum rounded up):
+//   [0] split: sum_i |x_ij| 4 (ks - k_i), unit i entering at K step k_i = 2 (i / 32) +
+//       ((i % 16) >= 8) (the operand record layout) and passing through at most 4 (ks - k_i)
+//       rounding steps (two MFMA halves per plane, two planes per K step);
+//   [1] split: sum over K steps and MFMA halves of the largest |x_ij| of the half (half h of
+//       step k holds units base + 4h + t and base + 16 + 4h + t, t < 4, base = 32 (k / 2) +
+//       8 (k % 2)): the dropped bits of a half-sum are bounded by its largest product;
+//   [2] split: max(sum of the positive, sum of the negative) residuals x - hi - lo: no treated
+//       set sums to more than either;
+//   [3] fp32: sum_i |x_ij| (ks - i / 16), the VALU running-total adds unit i passes through;
+//   [4] fp32: max(sum of the positive, sum of the negative) residuals x - float(x).
+__global__ void bound_sums_kernel(const double* X, int64_t n, int64_t d, int64_t ks, double* out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= d) return;
+    auto x = [&](int64_t i) -> double { return i < n ? X[i * d + j] : 0.0; };
+    double wsplit = 0.0, rsp = 0.0, rsn = 0.0, wf = 0.0, rfp = 0.0, rfn = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double v = x(i), a = fabs(v);
+        const int64_t ki = 2 * (i / 32) + ((i % 16) >= 8 ? 1 : 0);
+        wsplit += a * (double)(4 * (ks - ki));
+        wf += a * (double)(ks - i / 16);
+        // the operand records' hi / lo: exact differences in FP64
+        const double hi = (double)bf16_to_float(bf16_rne((float)v));
+        const double r1 = v - hi;
+        const double r = r1 - (double)bf16_to_float(bf16_rne((float)r1));
+        if (r > 0) rsp += r; else rsn -= r;
+        const double rf = v - (double)(float)v;
+        if (rf > 0) rfp += rf; else rfn -= rf;
+    }
+    double tsplit = 0.0;
+    for (int64_t k = 0; k < ks; ++k) {
+        const int64_t base = 32 * (k / 2) + 8 * (k % 2);
+        for (int h = 0; h < 2; ++h) {
+            double m = 0.0;
+            for (int t = 0; t < 4; ++t) m = fmax(m, fmax(fabs(x(base + 4 * h + t)), fabs(x(base + 16 + 4 * h + t))));
+            tsplit += m;
+        }
+    }
+    const double up = 1.0 + 1e-12;   // cover the FP64 rounding of the sums
+    out[j] = wsplit * up;
+    out[d + j] = tsplit * up;
+    out[2 * d + j] = fmax(rsp, rsn) * up;
+    out[3 * d + j] = wf * up;
+    out[4 * d + j] = fmax(rfp, rfn) * up;
+}
+
 static hipError_t gemm_nt(hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                           int64_t sam, int64_t sak, const double* B, int64_t sbn, int64_t sbk, double beta,
                           double* C, int64_t ldc) {
@@ -381,7 +429,7 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     RR_PHIP(hipMalloc(&P.cabs, sizeof(float) * dpad));
     RR_PHIP(hipMalloc(&P.op_i8, sizeof(uint4) * kRecordU4I8 * P.ks * P.ncb));
     RR_PHIP(hipMalloc(&P.bscale, sizeof(float) * P.ncb));
-    RR_PHIP(hipMalloc(&qe, sizeof(double) * d));
+    RR_PHIP(hipMalloc(&qe, sizeof(double) * 6 * d));   // e_j, then the five bound sums
     RR_PHIP(hipMalloc(&piv, sizeof(double) * d));
     RR_PHIP(hipMalloc(&scal, sizeof(double) * 2));
     RR_PHIP(hipMalloc(&bad, sizeof(int)));
@@ -452,11 +500,14 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     RR_PHIP(hipGetLastError());
     hipLaunchKernelGGL(qerr_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, P.X64, n, d, P.bscale, qe);
     RR_PHIP(hipGetLastError());
+    hipLaunchKernelGGL(bound_sums_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, P.X64, n, d, P.ks,
+                       qe + d);
+    RR_PHIP(hipGetLastError());
     {
         std::vector<float> hc((size_t)dpad);
-        std::vector<double> he((size_t)d);
+        std::vector<double> he((size_t)(6 * d));
         RR_PHIP(hipMemcpyAsync(hc.data(), P.cabs, sizeof(float) * dpad, hipMemcpyDeviceToHost, st));
-        RR_PHIP(hipMemcpyAsync(he.data(), qe, sizeof(double) * d, hipMemcpyDeviceToHost, st));
+        RR_PHIP(hipMemcpyAsync(he.data(), qe, sizeof(double) * 6 * d, hipMemcpyDeviceToHost, st));
         RR_PHIP(hipStreamSynchronize(st));
         double c2 = 0.0, cmax = 0.0;
         for (float c : hc) {
@@ -466,12 +517,29 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
         P.cabs_c2 = c2;
         P.cabs_max = cmax;
         double e2 = 0.0, emax = 0.0;
-        for (double e : he) {
-            e2 += e * e;
-            emax = std::max(emax, e);
+        for (int64_t j = 0; j < d; ++j) {
+            e2 += he[j] * he[j];
+            emax = std::max(emax, he[j]);
         }
         P.qerr_c2 = e2 * (1.0 + 1e-12);
         P.qerr_max = emax;
+        // per-column bounds of |G32_j - G_j| of the split and FP32 contractions (rounding model
+        // and constants in bound_constants)
+        std::vector<double> es((size_t)d), ef((size_t)d);
+        for (int64_t j = 0; j < d; ++j) {
+            es[j] = split_column_bound(P, he[d + j], he[2 * d + j], he[3 * d + j]);
+            ef[j] = fp32_column_bound(P, (double)hc[j], he[4 * d + j], he[5 * d + j]);
+        }
+        auto norm2 = [](const std::vector<double>& v) {
+            double s2 = 0.0, m = 0.0;
+            for (double x : v) {
+                s2 += x * x;
+                m = std::max(m, x);
+            }
+            return std::make_pair(s2 * (1.0 + 1e-12), m);
+        };
+        std::tie(P.esplit_n2, P.esplit_max) = norm2(es);
+        std::tie(P.ef32_n2, P.ef32_max) = norm2(ef);
     }
     hipFree(qe);
     hipFree(S);

@@ -366,7 +366,69 @@ struct WS {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Resources of a released handle kept for the next handle on the same device: the draw
+// pipeline's workspace, the auxiliary workspace, the generation stream and the events.  A
+// caller that prepares a new problem for every pool (as one step of the benchmark does) then
+// allocates none of them again.  One slot per device; a newer release replaces what the slot
+// holds (those buffers are freed then), and the slot lives until the process ends.
+namespace {
+struct Parked {
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    void* aux = nullptr;
+    size_t aux_bytes = 0;
+    hipStream_t gen_stream = nullptr;
+    std::vector<hipEvent_t> events;
+};
+std::mutex g_park_mu;
+Parked g_parked[64];
+
+void release_parked(Parked& s) {
+    if (s.ws) hipFree(s.ws);
+    if (s.aux) hipFree(s.aux);
+    for (hipEvent_t e : s.events) hipEventDestroy(e);
+    if (s.gen_stream) hipStreamDestroy(s.gen_stream);
+    s = Parked{};
+}
+}  // namespace
+
+// Takes the parked resources of the handle's device, if the handle has none of its own.
+static void adopt_parked(Problem& P) {
+    if (P.device < 0 || P.device >= 64 || P.ws || P.aux || P.gen_stream || !P.events.empty()) return;
+    std::lock_guard<std::mutex> g(g_park_mu);
+    Parked& s = g_parked[P.device];
+    P.ws = s.ws;
+    P.ws_bytes = s.ws_bytes;
+    P.aux = s.aux;
+    P.aux_bytes = s.aux_bytes;
+    P.gen_stream = s.gen_stream;
+    P.events = std::move(s.events);
+    s = Parked{};
+}
+
+// Parks a released handle's resources (the device is idle: rr_free synchronised it).
+static void park(Problem& P) {
+    if (!P.ws && !P.aux && !P.gen_stream && P.events.empty()) return;   // nothing to keep
+    if (P.device < 0 || P.device >= 64) {
+        Parked tmp{P.ws, P.ws_bytes, P.aux, P.aux_bytes, P.gen_stream, std::move(P.events)};
+        release_parked(tmp);
+        return;
+    }
+    std::lock_guard<std::mutex> g(g_park_mu);
+    Parked& s = g_parked[P.device];
+    release_parked(s);
+    s.ws = P.ws;
+    s.ws_bytes = P.ws_bytes;
+    s.aux = P.aux;
+    s.aux_bytes = P.aux_bytes;
+    s.gen_stream = P.gen_stream;
+    s.events = std::move(P.events);
+    P.ws = P.aux = nullptr;
+    P.gen_stream = nullptr;
+}
+
 static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint32_t band_cap, size_t bits_words, WS* w) {
+    adopt_parked(P);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -415,6 +477,7 @@ static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint
 }
 
 rr_status ensure_aux(Problem& P, size_t bytes) {
+    adopt_parked(P);
     bytes = align256(std::max<size_t>(bytes, 256));
     if (bytes <= P.aux_bytes) return RR_OK;
     if (P.aux) RR_HIP(hipDeviceSynchronize());
@@ -442,7 +505,8 @@ rr_status ensure_aux(Problem& P, size_t bytes) {
 //          |x - hi - lo| <= 2^-18 |x|;
 //   fp32:  K steps start from zero (16 rounding steps inside a step) and are summed on the
 //          VALU (ks steps): gamma(16 + ks) sum|x32|, and |x - x32| <= 2^-24 |x|.
-// Hence |G32_j - G_j| <= kappa cabs_j with cabs_j = sum_i |X~_ij| >= the treated sum.  M32
+// Hence |G32_j - G_j| <= kappa cabs_j with cabs_j = sum_i |X~_ij| >= the treated sum (the
+// split and FP32 forms use the tighter per-column bounds e_j below in place of kappa cabs_j).  M32
 // errs by at most scale (2 kappa sum_j |G32_j| cabs_j + kappa^2 sum_j cabs_j^2) plus the
 // FP32 sum of squares (gamma(depth) M32); the kernel bounds sum_j |G32_j| cabs_j by
 // ||G32|| ||cabs|| (Cauchy-Schwarz), and the assembled bound is multiplied by kSafety = 4:
@@ -453,6 +517,31 @@ constexpr double kU = 0x1p-24;
 constexpr double kSafety = 4.0;
 
 static double gamma_m(double m) { return m * kU / (1.0 - m * kU); }
+
+// Per-column bounds e_j of |G32_j - G_j|, tighter than kappa cabs_j (the same rounding model):
+//   rounding: a step errs by at most u times the partial sum so far, which holds only the units
+//     already added, so the rounding part is u' sum_i |x_ij| (steps unit i passes through),
+//     u' = u / (1 - m u) with m the chain length (the step-weighted sum from the preparation);
+//   dropped bits (BF16): each half-sum loses less than 7 x 2^-23 times its largest product
+//     (twice the measured window), summed over the halves (sum of per-half maxima), compounded
+//     through the chain;
+//   representation: the exact residuals x - hi - lo (x - float(x) for FP32), of which a treated
+//     set sums at most all the positive or all the negative ones.
+// FP32: 16 rounding steps inside each K step on its own units, plus the VALU running total.
+double split_column_bound(const Problem& P, double wsum_j, double halfmax_j, double resid_j) {
+    const double m = 4.0 * (double)P.ks;
+    const double up = kU / (1.0 - m * kU);
+    const double planes = 1.0 + 0x1p-8 + 0x1p-16;   // |hi| + |lo| <= |x| (1 + 2^-8 + 2^-18)
+    const double round = up * planes * wsum_j;
+    const double dropped = 7.0 * 0x1p-23 * planes * halfmax_j * (1.0 + gamma_m(m));
+    return (round + dropped + resid_j * (1.0 + gamma_m(m))) * (1.0 + 1e-9);
+}
+
+double fp32_column_bound(const Problem& P, double cabs_j, double wsum_j, double resid_j) {
+    const double m = 16.0 + (double)P.ks;
+    const double up = kU / (1.0 - m * kU);
+    return (up * (1.0 + 0x1p-23) * (16.0 * cabs_j + wsum_j) + resid_j * (1.0 + gamma_m(m))) * (1.0 + 1e-9);
+}
 
 Bound bound_constants(const Problem& P, int prec) {
     const double ks = (double)P.ks;
@@ -475,12 +564,8 @@ Bound bound_constants(const Problem& P, int prec) {
         b.safety = 1.0f;   // no MFMA rounding model involved: the int32 sums are exact
         return b;
     }
-    double kappa;
-    if (prec == RR_PREC_SPLIT_BF16 || prec == RR_PREC_GRAM_BF16)
-        kappa = (gamma_m(4.0 * ks) + gamma_m(14.0)) * (1.0 + 0x1p-8 + 0x1p-16) + 1.05 * 0x1p-18;
-    else
-        kappa = gamma_m(16.0 + ks) * (1.0 + 0x1p-23) + 0x1p-24;
     if (prec == RR_PREC_GRAM_BF16) {
+        const double kappa = (gamma_m(4.0 * ks) + gamma_m(14.0)) * (1.0 + 0x1p-8 + 0x1p-16) + 1.05 * 0x1p-18;
         // G'_j = sum_{i in T} K_ij errs by at most kappa cabsK_j; M = scale sum_{j in T} G'_j, so
         // |M32 - M| <= scale (kappa sum_{j in T} cabsK_j + gamma(depth) sum_{j in T} |G'32_j|),
         // and sum_{j in T} cabsK_j <= the sum of the n1 largest column sums (gram_ctop).
@@ -495,14 +580,16 @@ Bound bound_constants(const Problem& P, int prec) {
         b.safety = (float)kSafety;
         return b;
     }
-    const double c2 = mx ? P.cabs_max * P.cabs_max : P.cabs_c2;
+    // sum_j e_j^2 (largest e_j^2 for the per-column criterion) of the per-column bounds
+    const double e2 = prec == RR_PREC_SPLIT_BF16 ? (mx ? P.esplit_max * P.esplit_max : P.esplit_n2)
+                                                 : (mx ? P.ef32_max * P.ef32_max : P.ef32_n2);
     const int cb = draw_cb(prec, P.S);
     const int chunks = (int)((P.ncb + cb - 1) / cb);
     const double depth_ss = 16.0 * cb + chunks + 4.0;
     Bound b;
-    b.two_kappa = (float)(2.0 * kappa * (1.0 + gamma_m(depth_ss)) * (1.0 + 1e-6));
-    b.csq = (float)(kappa * kappa * c2 * 1.01);
-    b.cnorm = (float)(std::sqrt(c2) * (1.0 + 1e-6));
+    b.two_kappa = (float)(2.0 * (1.0 + gamma_m(depth_ss)) * (1.0 + 1e-6));
+    b.csq = (float)(e2 * 1.01);
+    b.cnorm = (float)(std::sqrt(e2) * (1.0 + 1e-6));
     b.gamma_ss = (float)(gamma_m(depth_ss) * 1.01);
     b.safety = (float)kSafety;
     return b;
@@ -542,6 +629,7 @@ ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b) {
 // (default priority) and overlaps the contraction of the previous chunk on the caller's
 // stream; events order the double-buffered bitmask chunks.
 static rr_status ensure_streams(Problem& P, size_t nevents) {
+    adopt_parked(P);
     if (!P.gen_stream) RR_HIP(hipStreamCreateWithFlags(&P.gen_stream, hipStreamNonBlocking));
     while (P.events.size() < nevents) {
         hipEvent_t e;
@@ -891,10 +979,7 @@ void rr_free(rr_problem* p) {
     hipFree(P.bscale);
     hipFree(P.op_gram);
     hipFree(P.cabs);
-    hipFree(P.ws);
-    hipFree(P.aux);
-    for (hipEvent_t e : P.events) hipEventDestroy(e);
-    if (P.gen_stream) hipStreamDestroy(P.gen_stream);
+    park(P);   // workspace, streams and events go to the next handle on this device
     free_batch_state(P);
     delete p;
 }
