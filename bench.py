@@ -164,7 +164,8 @@ def run_batched(args, rr, inputs, np, torch):
         "mfma_tflops_over_graph": achieved, "frac_bf16_peak_over_graph": achieved / PEAK_BF16_TFLOPS,
         "per_pool_calls": {"ms": loop_ms, "draws_per_s": total / (loop_ms / 1000.0),
                            "batched_speedup": loop_ms / ms_per_step, "same_results_sampled": same},
-        "prepare_s_all_pools": prep_s, "i8_form": i8}), flush=True)
+        "prepare_s_all_pools": prep_s, "i8_form": i8,
+        "tuner_batched_classes": [e for e in rr.rr_tune_report()["rr_tune"] if e["batched"] == 1]}), flush=True)
 
 
 def run_alone(args, rr, torch, w, Xd):
@@ -361,6 +362,7 @@ def main():
         "roofline": roofline, "cpu_baseline": base, "fp32_form": fp32, "i8_form": i8, "split_form": split,
         "contract_kernel_ms_per_step": contract_ms / args.steps, "guard_band": band,
         "rand_test_counts_min": int(counts.min().item()) if counts is not None else None,
+        "tuner": [e for e in rr.rr_tune_report()["rr_tune"] if e["batched"] == 0],
     }
     print(json.dumps(out), flush=True)
 

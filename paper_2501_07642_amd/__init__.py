@@ -12,6 +12,6 @@ from ._lib import (  # noqa: F401
     RRError, Problem,
     lib_path, load, rr_balance_keys, rr_balance_keys_noalloc, rr_draw_balance, rr_draw_balance_async, rr_draw_balance_batched,
     rr_diagnose, rr_draw_exact, rr_last_timing, rr_prepare, rr_q_star, rr_rand_test, rr_rand_test_interval,
-    rr_realized_rmse,
+    rr_realized_rmse, rr_tune_report,
     rr_regenerate, quantile_count,
 )

@@ -35,6 +35,7 @@ SIGNATURES = [
                                    C.POINTER(_I), _P]),
     ("rr_draw_balance_batched", _I, [_P, _I64, _P, _U64, _U64, _I, _D, _I, _P, _P, _U64, _P, _P]),
     ("rr_last_timing", _I, [C.POINTER(_D), C.POINTER(_D), C.POINTER(_D), C.POINTER(_I64), C.POINTER(_U64)]),
+    ("rr_tune_report", _I, [C.c_char_p, _U64, C.POINTER(_U64)]),
     ("rr_diagnose", _I, [_I64, _I64, _I64, _D, _D, _D, _P]),
     ("rr_q_star", _I, [_I64, _I64, _I64, _D, _D, _D, _D, _D, _D, C.POINTER(_D)]),
     ("rr_realized_rmse", _I, [_I64, _I64, _I64, _D, _D, _D, C.POINTER(_D), C.POINTER(_D)]),
@@ -297,6 +298,16 @@ def rr_last_timing():
     t, ck, gk, nl, band = C.c_double(), C.c_double(), C.c_double(), C.c_int64(), C.c_uint64()
     _check(load().rr_last_timing(C.byref(t), C.byref(ck), C.byref(gk), C.byref(nl), C.byref(band)))
     return dict(total_ms=t.value, contract_ms=ck.value, gen_ms=gk.value, launches=nl.value, band=band.value)
+
+
+def rr_tune_report():
+    """The autotuner's choices of this process (dict parsed from the library's JSON report)."""
+    import json
+    need = C.c_uint64()
+    load().rr_tune_report(None, 0, C.byref(need))
+    buf = C.create_string_buffer(max(int(need.value), 1))
+    _check(load().rr_tune_report(buf, len(buf), C.byref(need)))
+    return json.loads(buf.value.decode())
 
 
 def rr_diagnose(n1, n0, d, q, sigma=1.0, r2=0.0):

@@ -316,10 +316,11 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         std::stable_sort(g.idx.begin(), g.idx.end(), [&](int64_t x, int64_t y) {
             return P[x]->P.ks * P[x]->P.ncb > P[y]->P.ks * P[y]->P.ncb;
         });
-        // Default tiles, not the single-pool probe: a group's generation and contraction run
-        // side by side over many pools, and the choice that is fastest for one pool alone
-        // (for S = 4, one draw tile per wave with four generation workgroups per CU) measured
-        // about 10% slower in this launch than the default two tiles with three.
+        // Default tiles to start from, not the single-pool choice: a class's generation and
+        // contraction run side by side over many pools, and the choice that is fastest for one
+        // pool alone (for S = 4, one draw tile per wave with four generation workgroups per CU)
+        // measured about 10% slower in this launch than two tiles with three; the batched
+        // tuner below measures each class inside the graph instead.
         g.tune = tune_default(precision, S, true);
         g.tile = contract_tile(precision, S, g.tune.db);
         groups.push_back(g);
@@ -509,131 +510,188 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
     RR_HIP(hipMemcpyAsync(d_pr, pr.data(), sizeof(PoolRec) * pr.size(), hipMemcpyHostToDevice, B.s_main));
     RR_HIP(hipStreamSynchronize(B.s_main));
 
-    // ---- graph: captured once per distinct argument set
-    std::vector<uint64_t> sig;
-    sig.push_back((uint64_t)nprob);
-    sig.push_back(key_begin);
-    sig.push_back(N);
-    sig.push_back((uint64_t)mode | (chi2 ? 0x100u : 0u));
-    uint64_t qbits;
-    std::memcpy(&qbits, &q_or_a, 8);
-    sig.push_back(qbits);
-    sig.push_back((uint64_t)precision);
-    sig.push_back(capacity);
-    sig.push_back((uint64_t)(uintptr_t)B.ws);
-    sig.push_back(C);
-    for (int64_t i = 0; i < nprob; ++i) {
-        // the handle's process-unique id, not its address: a freed handle's address can be
-        // reused by a new problem of another shape, whose S group, tile grid and operands the
-        // captured launches would not match
-        sig.push_back(P[i]->P.uid);
-        sig.push_back(seeds[i]);
-        sig.push_back((uint64_t)(uintptr_t)d_keys[i]);
-        sig.push_back((uint64_t)(uintptr_t)d_M[i]);
-    }
-    for (const Group& g : groups) sig.push_back(((uint64_t)g.tune.db << 32) | (uint32_t)g.tune.gen_wg);
-    if (!B.exec || sig != B.sig) {
-        if (B.exec) hipGraphExecDestroy(B.exec);
-        if (B.graph) hipGraphDestroy(B.graph);
-        B.exec = nullptr;
-        B.graph = nullptr;
-        B.sig.clear();
-        const size_t nev = 2 * R * groups.size() + 4;
-        while (B.ev.size() < nev) {
-            hipEvent_t e;
-            RR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-            B.ev.push_back(e);
+    // ---- graph: captured once per distinct argument set (tiles included), then launched,
+    // ordered after the caller's stream and before its later work; returns the graph's GPU time
+    auto launch_graph = [&](float* out_ms) -> rr_status {
+        std::vector<uint64_t> sig;
+        sig.push_back((uint64_t)nprob);
+        sig.push_back(key_begin);
+        sig.push_back(N);
+        sig.push_back((uint64_t)mode | (chi2 ? 0x100u : 0u));
+        uint64_t qbits;
+        std::memcpy(&qbits, &q_or_a, 8);
+        sig.push_back(qbits);
+        sig.push_back((uint64_t)precision);
+        sig.push_back(capacity);
+        sig.push_back((uint64_t)(uintptr_t)B.ws);
+        sig.push_back(C);
+        for (int64_t i = 0; i < nprob; ++i) {
+            // the handle's process-unique id, not its address: a freed handle's address can be
+            // reused by a new problem of another shape, whose S group, tile grid and operands the
+            // captured launches would not match
+            sig.push_back(P[i]->P.uid);
+            sig.push_back(seeds[i]);
+            sig.push_back((uint64_t)(uintptr_t)d_keys[i]);
+            sig.push_back((uint64_t)(uintptr_t)d_M[i]);
         }
-        hipEvent_t* ready = B.ev.data();                          // [r][group]
-        hipEvent_t* freed = B.ev.data() + R * groups.size();      // [r][group]
-        hipEvent_t fork = B.ev[2 * R * groups.size()], join = B.ev[2 * R * groups.size() + 1];
-        hipEvent_t fork2 = B.ev[2 * R * groups.size() + 2], join2 = B.ev[2 * R * groups.size() + 3];
-        int64_t kernels = 0;
-        hipError_t e = hipStreamBeginCapture(B.s_main, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) {
-            set_error(std::string("rr_draw_balance_batched: graph capture: ") + hipGetErrorString(e));
-            return RR_E_DEVICE;
-        }
-        auto check = [&](hipError_t x) {
-            if (e == hipSuccess) e = x;
-        };
-        hipLaunchKernelGGL(batch_init_kernel, dim3((unsigned)((nprob + 255) / 256)), dim3(256), 0, B.s_main, d_st,
-                           (int)nprob, (uint32_t)k);
-        check(hipGetLastError());
-        ++kernels;
-        check(hipEventRecord(fork, B.s_main));
-        check(hipStreamWaitEvent(B.s_gen, fork, 0));
-        for (uint64_t r = 0; r < R && e == hipSuccess; ++r) {
-            const uint64_t cnt = rcnt[r];
-            for (size_t gi = 0; gi < groups.size(); ++gi) {
-                const Group& g = groups[gi];
-                const uint64_t m = g.idx.size();
-                if (r >= 2) check(hipStreamWaitEvent(B.s_gen, freed[(r - 2) * groups.size() + gi], 0));
-                const uint64_t gen_wgs = std::min<uint64_t>((m * cnt + 3) / 4, (uint64_t)cus * g.tune.gen_wg);
-                check(launch_gen_batch(g.S, d_gt + r * np + gpos[gi], m, cnt, (int)gen_wgs, B.s_gen));
-                check(hipEventRecord(ready[r * groups.size() + gi], B.s_gen));
-                check(hipStreamWaitEvent(B.s_main, ready[r * groups.size() + gi], 0));
-                ContractArgs a0{};
-                a0.tab = d_ct + r * np + gpos[gi];
-                a0.tpp = (uint32_t)((cnt + g.tile - 1) / g.tile);
-                a0.nprob = (uint32_t)m;
-                const uint64_t tiles = m * a0.tpp;
-                check(launch_contract(g.S, precision, g.tune.db, true, a0, (int)std::min<uint64_t>(tiles, cus),
-                                      B.s_main));
-                check(hipEventRecord(freed[r * groups.size() + gi], B.s_main));
-                kernels += 2;
-            }
-        }
-        check(hipEventRecord(join, B.s_gen));
-        check(hipStreamWaitEvent(B.s_main, join, 0));
-        hipLaunchKernelGGL(batch_select_kernel, dim3((unsigned)nprob), dim3(1024), 0, B.s_main, d_pr, (uint32_t)N,
-                           mode);
-        check(hipGetLastError());
-        ++kernels;
-        // the groups' rechecks are independent: alternate them over the two streams
-        check(hipEventRecord(fork2, B.s_main));
-        check(hipStreamWaitEvent(B.s_gen, fork2, 0));
-        for (size_t gi = 0; gi < groups.size(); ++gi) {
-            const int rgrid = kBatchRecheckWgsPerCu * cus;
-            check(launch_recheck_batch(groups[gi].S, d_rt + gpos[gi], (int)groups[gi].idx.size(),
-                                       d_off + gpos[gi] + gi, rgrid, (gi & 1) ? B.s_gen : B.s_main));
-            kernels += 2;
-            if (any_refine) {
-                check(launch_recheck_batch(groups[gi].S, d_rta + gpos[gi], (int)groups[gi].idx.size(),
-                                           d_off + noff + gpos[gi] + gi, rgrid, (gi & 1) ? B.s_gen : B.s_main));
-                kernels += 2;
-            }
-        }
-        check(hipEventRecord(join2, B.s_gen));
-        check(hipStreamWaitEvent(B.s_main, join2, 0));
-        hipLaunchKernelGGL(batch_finish_kernel, dim3((unsigned)nprob), dim3(1024), 0, B.s_main, d_pr, mode);
-        check(hipGetLastError());
-        ++kernels;
-        hipGraph_t graph = nullptr;
-        const hipError_t e2 = hipStreamEndCapture(B.s_main, &graph);
-        if (e == hipSuccess) e = e2;
-        if (e == hipSuccess) e = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            if (graph) hipGraphDestroy(graph);
+        for (const Group& g : groups) sig.push_back(((uint64_t)g.tune.db << 32) | (uint32_t)g.tune.gen_wg);
+        if (!B.exec || sig != B.sig) {
+            if (B.exec) hipGraphExecDestroy(B.exec);
+            if (B.graph) hipGraphDestroy(B.graph);
             B.exec = nullptr;
-            set_error(std::string("rr_draw_balance_batched: graph build: ") + hipGetErrorString(e));
-            return RR_E_DEVICE;
+            B.graph = nullptr;
+            B.sig.clear();
+            const size_t nev = 2 * R * groups.size() + 4;
+            while (B.ev.size() < nev) {
+                hipEvent_t e;
+                RR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                B.ev.push_back(e);
+            }
+            hipEvent_t* ready = B.ev.data();                          // [r][group]
+            hipEvent_t* freed = B.ev.data() + R * groups.size();      // [r][group]
+            hipEvent_t fork = B.ev[2 * R * groups.size()], join = B.ev[2 * R * groups.size() + 1];
+            hipEvent_t fork2 = B.ev[2 * R * groups.size() + 2], join2 = B.ev[2 * R * groups.size() + 3];
+            int64_t kernels = 0;
+            hipError_t e = hipStreamBeginCapture(B.s_main, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) {
+                set_error(std::string("rr_draw_balance_batched: graph capture: ") + hipGetErrorString(e));
+                return RR_E_DEVICE;
+            }
+            auto check = [&](hipError_t x) {
+                if (e == hipSuccess) e = x;
+            };
+            hipLaunchKernelGGL(batch_init_kernel, dim3((unsigned)((nprob + 255) / 256)), dim3(256), 0, B.s_main, d_st,
+                               (int)nprob, (uint32_t)k);
+            check(hipGetLastError());
+            ++kernels;
+            check(hipEventRecord(fork, B.s_main));
+            check(hipStreamWaitEvent(B.s_gen, fork, 0));
+            for (uint64_t r = 0; r < R && e == hipSuccess; ++r) {
+                const uint64_t cnt = rcnt[r];
+                for (size_t gi = 0; gi < groups.size(); ++gi) {
+                    const Group& g = groups[gi];
+                    const uint64_t m = g.idx.size();
+                    if (r >= 2) check(hipStreamWaitEvent(B.s_gen, freed[(r - 2) * groups.size() + gi], 0));
+                    const uint64_t gen_wgs = std::min<uint64_t>((m * cnt + 3) / 4, (uint64_t)cus * g.tune.gen_wg);
+                    check(launch_gen_batch(g.S, d_gt + r * np + gpos[gi], m, cnt, (int)gen_wgs, B.s_gen));
+                    check(hipEventRecord(ready[r * groups.size() + gi], B.s_gen));
+                    check(hipStreamWaitEvent(B.s_main, ready[r * groups.size() + gi], 0));
+                    ContractArgs a0{};
+                    a0.tab = d_ct + r * np + gpos[gi];
+                    a0.tpp = (uint32_t)((cnt + g.tile - 1) / g.tile);
+                    a0.nprob = (uint32_t)m;
+                    const uint64_t tiles = m * a0.tpp;
+                    check(launch_contract(g.S, precision, g.tune.db, true, a0, (int)std::min<uint64_t>(tiles, cus),
+                                          B.s_main));
+                    check(hipEventRecord(freed[r * groups.size() + gi], B.s_main));
+                    kernels += 2;
+                }
+            }
+            check(hipEventRecord(join, B.s_gen));
+            check(hipStreamWaitEvent(B.s_main, join, 0));
+            hipLaunchKernelGGL(batch_select_kernel, dim3((unsigned)nprob), dim3(1024), 0, B.s_main, d_pr, (uint32_t)N,
+                               mode);
+            check(hipGetLastError());
+            ++kernels;
+            // the groups' rechecks are independent: alternate them over the two streams
+            check(hipEventRecord(fork2, B.s_main));
+            check(hipStreamWaitEvent(B.s_gen, fork2, 0));
+            for (size_t gi = 0; gi < groups.size(); ++gi) {
+                const int rgrid = kBatchRecheckWgsPerCu * cus;
+                check(launch_recheck_batch(groups[gi].S, d_rt + gpos[gi], (int)groups[gi].idx.size(),
+                                           d_off + gpos[gi] + gi, rgrid, (gi & 1) ? B.s_gen : B.s_main));
+                kernels += 2;
+                if (any_refine) {
+                    check(launch_recheck_batch(groups[gi].S, d_rta + gpos[gi], (int)groups[gi].idx.size(),
+                                               d_off + noff + gpos[gi] + gi, rgrid, (gi & 1) ? B.s_gen : B.s_main));
+                    kernels += 2;
+                }
+            }
+            check(hipEventRecord(join2, B.s_gen));
+            check(hipStreamWaitEvent(B.s_main, join2, 0));
+            hipLaunchKernelGGL(batch_finish_kernel, dim3((unsigned)nprob), dim3(1024), 0, B.s_main, d_pr, mode);
+            check(hipGetLastError());
+            ++kernels;
+            hipGraph_t graph = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(B.s_main, &graph);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                if (graph) hipGraphDestroy(graph);
+                B.exec = nullptr;
+                set_error(std::string("rr_draw_balance_batched: graph build: ") + hipGetErrorString(e));
+                return RR_E_DEVICE;
+            }
+            B.graph = graph;
+            B.sig = sig;
+            B.kernels = kernels;
         }
-        B.graph = graph;
-        B.sig = sig;
-        B.kernels = kernels;
-    }
 
-    // ---- launch, ordered after the caller's stream and before its later work
-    RR_HIP(hipEventRecord(B.join, st));
-    RR_HIP(hipStreamWaitEvent(B.s_main, B.join, 0));
-    RR_HIP(hipEventRecord(B.t0, B.s_main));
-    RR_HIP(hipGraphLaunch(B.exec, B.s_main));
-    RR_HIP(hipEventRecord(B.t1, B.s_main));
-    RR_HIP(hipStreamSynchronize(B.s_main));
+        RR_HIP(hipEventRecord(B.join, st));
+        RR_HIP(hipStreamWaitEvent(B.s_main, B.join, 0));
+        RR_HIP(hipEventRecord(B.t0, B.s_main));
+        RR_HIP(hipGraphLaunch(B.exec, B.s_main));
+        RR_HIP(hipEventRecord(B.t1, B.s_main));
+        RR_HIP(hipStreamSynchronize(B.s_main));
+        RR_HIP(hipEventElapsedTime(out_ms, B.t0, B.t1));
+        return RR_OK;
+    };
+
+    // ---- per-class tiles measured inside this graph: the cached choice of each bitmask class,
+    // else (on a call of at least 2^24 draws in total) coordinate descent over the classes,
+    // largest work first: every (db, gen_wg) candidate of a class runs the whole graph twice
+    // with the other classes as they stand, the faster of the two GPU times counting
     float graph_ms = 0.f;
-    RR_HIP(hipEventElapsedTime(&graph_ms, B.t0, B.t1));
-
+    {
+        std::vector<char> known(groups.size(), 0);
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            Tune t{};
+            if (batch_tune_lookup(precision, groups[gi].S, &t)) {
+                groups[gi].tune = t;
+                groups[gi].tile = contract_tile(precision, groups[gi].S, t.db);
+                known[gi] = 1;
+            }
+        }
+        const bool probe = tuning_on() && (uint64_t)nprob * N >= (1ull << 24) &&
+                           std::find(known.begin(), known.end(), 0) != known.end();
+        if (probe) {
+            std::vector<size_t> order(groups.size());
+            std::vector<double> work(groups.size(), 0.0);
+            for (size_t gi = 0; gi < groups.size(); ++gi) {
+                order[gi] = gi;
+                for (int64_t i : groups[gi].idx) work[gi] += (double)P[i]->P.ks * (double)P[i]->P.ncb;
+            }
+            std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return work[x] > work[y]; });
+            for (size_t gi : order) {
+                if (known[gi]) continue;
+                Group& g = groups[gi];
+                Tune best = g.tune;
+                double best_ms = INFINITY;
+                for (int db = 1; db <= 2; ++db) {
+                    if (!contract_db_ok(precision, g.S, db)) continue;
+                    const int fit = gen_wg_fit(precision, g.S, db, true);
+                    for (int gw = std::min(2, fit); gw <= fit; ++gw) {
+                        g.tune = Tune{db, gw};
+                        g.tile = contract_tile(precision, g.S, db);
+                        float m1 = 0.f, m2 = 0.f;
+                        rr_status ls = launch_graph(&m1);
+                        if (ls == RR_OK) ls = launch_graph(&m2);
+                        if (ls != RR_OK) return ls;
+                        const double ms = std::min(m1, m2);
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            best = g.tune;
+                        }
+                    }
+                }
+                g.tune = best;
+                g.tile = contract_tile(precision, g.S, best.db);
+                batch_tune_store(precision, g.S, best, best_ms);
+            }
+        }
+        const rr_status ls = launch_graph(&graph_ms);
+        if (ls != RR_OK) return ls;
+    }
     std::vector<AcceptState> hs(np);
     RR_HIP(hipMemcpy(hs.data(), d_st, sizeof(AcceptState) * np, hipMemcpyDeviceToHost));
     uint64_t band_total = 0;

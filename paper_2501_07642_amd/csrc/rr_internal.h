@@ -176,8 +176,9 @@ rr_status ensure_gram(Problem& P, hipStream_t st);
 // Launch configuration of the draw pipeline, chosen by the autotuner per problem bucket:
 // draws per wave block of the contraction tile (db, 1 or 2) and generation workgroups per CU.
 struct Tune {
-    int db;
-    int gen_wg;
+    int db;                // 32-draw blocks per contraction wave
+    int gen_wg;            // generation workgroups per CU
+    int chunk_log2 = 20;   // draws per pipeline chunk (single-pool calls): 2^chunk_log2
 };
 // Generation workgroups per CU by default: three 4-wave workgroups (<= 64 VGPRs per wave up to
 // 1024 units) fit beside one 8-wave contraction workgroup (<= 168 VGPRs per wave, up to ~131 KB
@@ -241,6 +242,11 @@ ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b);
 Tune tune_default(int prec, int S, bool batch);
 // probe = false: the cached choice or the default, never a timed probe (asynchronous calls).
 Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t st, bool probe = true);
+// Batched launches: the cached per-class choice (precision, S) measured inside the graph, if any;
+// and recording one.
+bool batch_tune_lookup(int prec, int S, Tune* out);
+void batch_tune_store(int prec, int S, const Tune& t, double ms);
+bool tuning_on();
 rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begin, uint64_t N, int mode,
                         double q_or_a, int prec, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
                         uint64_t capacity, uint64_t* h_count, hipStream_t st, const Tune* tune,

@@ -702,21 +702,22 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         set_error("rr_draw: threshold is NaN");
         return RR_E_ARG;
     }
-    // Chunks of draws: the bitmasks of chunk c are generated on the internal stream while
-    // chunk c - 1 is contracted on the caller's stream.
-    uint64_t chunk = std::min<uint64_t>(std::max<uint64_t>((N + 3) / 4, 1u << 16), 1u << 20);
-    chunk = std::min<uint64_t>(chunk, N);
-    const uint64_t nchunks = (N + chunk - 1) / chunk;
-    const size_t wpd = 8ull * P.S;
-    const uint32_t cand_cap = (uint32_t)std::max<uint64_t>(chunk + (1u << 20), 1u << 23);
-    const uint32_t acc_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(capacity, 1), cand_cap);
-    const uint32_t band_cap = 1u << 20;
     rr_status s = RR_OK;
     if (prec == RR_PREC_GRAM_BF16 && (s = ensure_gram(P, st)) != RR_OK) return s;
     // The launch configuration is settled before any workspace pointer is taken: a first call
     // of a tuning bucket probes candidates by running this pipeline on the same handle, and
     // those runs may grow (reallocate) the workspace and the event list.
     const Tune tn = tune ? *tune : tune_for(P, prec, exact, N, st, !async);
+    // Chunks of draws: the bitmasks of chunk c are generated on the internal stream while chunk
+    // c - 1 is contracted on the caller's stream (at least four chunks when N allows).
+    const int clog = std::min(21, std::max(16, tn.chunk_log2));
+    uint64_t chunk = std::min<uint64_t>(std::max<uint64_t>((N + 3) / 4, 1u << 16), 1ull << clog);
+    chunk = std::min<uint64_t>(chunk, N);
+    const uint64_t nchunks = (N + chunk - 1) / chunk;
+    const size_t wpd = 8ull * P.S;
+    const uint32_t cand_cap = (uint32_t)std::max<uint64_t>(chunk + (1u << 20), 1u << 23);
+    const uint32_t acc_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(capacity, 1), cand_cap);
+    const uint32_t band_cap = 1u << 20;
     WS w;
     if ((s = ensure_ws(P, cand_cap, acc_cap, band_cap, chunk * wpd, &w)) != RR_OK) return s;
     if ((s = ensure_streams(P, 4 * nchunks + 5)) != RR_OK) return s;

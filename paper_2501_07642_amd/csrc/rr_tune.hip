@@ -1,18 +1,29 @@
 // Autotuner of the draw pipeline's launch configuration.
 //
-// Tunables: the contraction tile (db = 32-draw blocks per wave, 1 or 2, where the tile's
-// bitmasks fit in LDS) and the generation kernel's workgroups per CU (2 up to the number that
-// fits beside one contraction workgroup by registers, at most 4).  Neither changes any
-// result: per-draw arithmetic depends only on the covariate chunking, which is fixed.
+// Tunables (none changes any result: per-draw arithmetic depends only on the covariate
+// chunking, which is fixed, and the acceptance is exact):
+//   db        the contraction tile, 32-draw blocks per wave (1 or 2, where the tile's bitmasks
+//             fit in LDS beside the operand stages);
+//   gen_wg    generation workgroups per CU, from 2 up to the number that fits beside one
+//             contraction workgroup by registers (at most 4);
+//   chunk     draws per pipeline chunk of a single-pool call, 2^19 .. 2^21 (longer chunks mean
+//             fewer launches and events; the first chunk's generation and the last chunk's
+//             contraction run without a partner, so shorter chunks waste less at the ends).
+// The waves per workgroup, covariate blocks per chunk and LDS stage depth are fixed by the
+// register and LDS budget (two 8-wave contraction workgroups' worth of waves per CU beside
+// three generation waves per SIMD) rather than tuned.
 //
-// Buckets: (precision, S = 256-unit chunks per draw, floor(log2(ks * ncb))), i.e. the
-// bitmask length and the MFMA work per draw.  On the first Monte Carlo call of a bucket that
-// covers at least 2^20 draws, every candidate runs the full two-stream pipeline on the calling
-// problem for a probe pool of 2^18 .. 2^20 draws (about 2^42 MFMA flops, so several chunks
-// overlap as in a long call), timed on the host around the synchronised call (best of two
-// after a warm-up run); the fastest wins.  Results live for the
-// process; with RR_TUNE_FILE set they are also read from and appended to that JSON file.
-// RR_TUNE=0 disables probing (defaults everywhere).
+// Single-pool buckets: (precision, S = 256-unit chunks per draw, floor(log2(ks * ncb))), i.e.
+// the bitmask length and the MFMA work per draw.  On the first Monte Carlo call of a bucket
+// that covers at least 2^20 draws, every (db, gen_wg) candidate runs the full two-stream
+// pipeline on the calling problem for a probe pool of 2^18 .. 2^20 draws (about 2^42 MFMA
+// flops), timed on the host around the synchronised call (best of two after a warm-up run);
+// then, for calls of at least 2^23 draws, the chunk length is chosen the same way on a 2^23-draw
+// pool with the winning tile.  Batched launches: per bitmask class (precision, S), the (db,
+// gen_wg) choice is measured inside the captured graph by rr_draw_balance_batched itself
+// (coordinate descent over the classes, graph time by HIP events).  Results live for the
+// process; with RR_TUNE_FILE set they are also read from and appended to that JSON file, and
+// rr_tune_report returns them.  RR_TUNE=0 disables probing (defaults everywhere).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -21,6 +32,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 
 #include "rr_internal.h"
@@ -46,7 +58,7 @@ Tune tune_default(int prec, int S, bool batch) {
 
 namespace {
 
-using Key = std::tuple<int, int, int>;   // precision, S, floor(log2(ks * ncb))
+using Key = std::tuple<int, int, int, int>;   // batched, precision, S, floor(log2(ks * ncb)) (-1 batched)
 
 struct Entry {
     Tune t;
@@ -77,7 +89,8 @@ bool tuning_enabled() {
     return !(e && std::strcmp(e, "0") == 0);
 }
 
-// One entry per line: {"prec": P, "S": S, "cost_log2": C, "db": D, "gen_wg": G, "ms": T}
+// One entry per line: {"batched": B, "prec": P, "S": S, "cost_log2": C, "db": D, "gen_wg": G,
+// "chunk_log2": L, "ms": T} ("batched" and "chunk_log2" may be missing: 0 and 20).
 void load_file() {
     g_loaded = true;
     const char* path = tune_file();
@@ -88,14 +101,40 @@ void load_file() {
     while (std::fgets(line, sizeof line, f)) {
         const char* p = std::strchr(line, '{');
         if (!p) continue;
-        int prec, S, cl, db, gw;
+        int batched = 0, prec, S, cl, db, gw, clog = 20;
         double ms;
-        if (std::sscanf(p, "{\"prec\": %d, \"S\": %d, \"cost_log2\": %d, \"db\": %d, \"gen_wg\": %d, \"ms\": %lf",
-                        &prec, &S, &cl, &db, &gw, &ms) == 6 &&
-            contract_db_ok(prec, S, db) && gw >= 1 && gw <= 8)
-            g_cache[Key(prec, S, cl)] = Entry{Tune{db, gw}, ms};
+        const char* q = std::strstr(p, "\"prec\"");
+        if (!q) continue;
+        if (const char* b = std::strstr(p, "\"batched\": ")) batched = std::atoi(b + 12);
+        if (const char* c = std::strstr(p, "\"chunk_log2\": ")) clog = std::atoi(c + 14);
+        const char* m = std::strstr(p, "\"ms\": ");
+        if (!m || std::sscanf(m, "\"ms\": %lf", &ms) != 1) continue;
+        if (std::sscanf(q, "\"prec\": %d, \"S\": %d, \"cost_log2\": %d, \"db\": %d, \"gen_wg\": %d", &prec, &S, &cl,
+                        &db, &gw) == 5 &&
+            contract_db_ok(prec, S, db) && gw >= 1 && gw <= 8 && clog >= 16 && clog <= 21) {
+            Tune t{db, gw};
+            t.chunk_log2 = clog;
+            g_cache[Key(batched ? 1 : 0, prec, S, cl)] = Entry{t, ms};
+        }
     }
     std::fclose(f);
+}
+
+std::string report_json() {
+    std::string out = "{\"rr_tune\": [\n";
+    size_t i = 0;
+    for (const auto& kv : g_cache) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf,
+                      "  {\"batched\": %d, \"prec\": %d, \"S\": %d, \"cost_log2\": %d, \"db\": %d, \"gen_wg\": %d, "
+                      "\"chunk_log2\": %d, \"ms\": %.4f}%s\n",
+                      std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                      kv.second.t.db, kv.second.t.gen_wg, kv.second.t.chunk_log2, kv.second.ms,
+                      ++i < g_cache.size() ? "," : "");
+        out += buf;
+    }
+    out += "]}\n";
+    return out;
 }
 
 void save_file() {
@@ -104,26 +143,22 @@ void save_file() {
     const std::string tmp = std::string(path) + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
-    std::fprintf(f, "{\"rr_tune\": [\n");
-    size_t i = 0;
-    for (const auto& kv : g_cache) {
-        std::fprintf(f, "  {\"prec\": %d, \"S\": %d, \"cost_log2\": %d, \"db\": %d, \"gen_wg\": %d, \"ms\": %.4f}%s\n",
-                     std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second.t.db,
-                     kv.second.t.gen_wg, kv.second.ms, ++i < g_cache.size() ? "," : "");
-    }
-    std::fprintf(f, "]}\n");
+    const std::string doc = report_json();
+    std::fputs(doc.c_str(), f);
     std::fclose(f);
     std::rename(tmp.c_str(), path);
 }
 
 }  // namespace
 
+bool tuning_on() { return tuning_enabled(); }
+
 Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t st, bool probe) {
     const Tune def = tune_default(prec, P.S, false);
     if (exact || !tuning_enabled()) return def;
     std::lock_guard<std::mutex> g(g_mu);
     if (!g_loaded) load_file();
-    const Key key(prec, P.S, cost_log2(P, prec));
+    const Key key(0, prec, P.S, cost_log2(P, prec));
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
         // entries read from a file may come from another build: keep them within the fit
@@ -133,14 +168,31 @@ Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t
     }
     if (work_draws < (1u << 20) || !probe) return def;
 
-    // probe pool: ~2^42 MFMA flops, 2^18 .. 2^20 draws
+    // One probe: the full pipeline on the calling problem, best of two timed runs after a
+    // warm-up run (the first run warms caches and code).
+    auto time_pool = [&](const Tune& t, uint64_t N, uint64_t* keys, double* M, uint64_t cap) {
+        double ms = INFINITY;
+        for (int rep = 0; rep < 3; ++rep) {
+            uint64_t cnt = 0;
+            const auto t0 = std::chrono::steady_clock::now();
+            const rr_status s = draw_pipeline(P, false, 0x7u, 0, N, RR_MODE_QUANTILE, 1e-4, prec, keys, M, nullptr,
+                                              cap, &cnt, st, &t);
+            const double dt = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (s != RR_OK) return (double)INFINITY;
+            if (rep > 0) ms = std::min(ms, dt);
+        }
+        return ms;
+    };
+    // probe pool for the tile and occupancy: ~2^42 MFMA flops, 2^18 .. 2^20 draws; the chunk
+    // stage uses 2^23 draws (four chunks of the longest length tried)
     const double ncb = (double)(prec == RR_PREC_GRAM_BF16 ? P.ncb_gram : P.ncb);
     const double flops_per_draw =
         2.0 * 16.0 * (double)P.ks * 32.0 * ncb * (prec == RR_PREC_SPLIT_BF16 || prec == RR_PREC_GRAM_BF16 ? 2.0 : 1.0);
     uint64_t N = (uint64_t)(std::ldexp(1.0, 42) / std::max(1.0, flops_per_draw));
     N = std::min<uint64_t>(std::max<uint64_t>(N, 1u << 18), 1u << 20);
-    const double q = 1e-3;
-    const uint64_t cap = (uint64_t)std::ceil(q * (double)N) + 1;
+    const uint64_t Nc = 1u << 23;
+    const bool chunk_stage = work_draws >= Nc && P.S <= 4;
+    const uint64_t cap = (uint64_t)std::ceil(1e-4 * (double)(chunk_stage ? Nc : N)) + 1;
     uint64_t* keys = nullptr;
     double* M = nullptr;
     if (hipMalloc(&keys, sizeof(uint64_t) * cap) != hipSuccess || hipMalloc(&M, sizeof(double) * cap) != hipSuccess) {
@@ -154,25 +206,27 @@ Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t
         const int fit = gen_wg_fit(prec, P.S, db, false);
         for (int gw = std::min(2, fit); gw <= fit; ++gw) {
             const Tune t{db, gw};
-            double ms = INFINITY;
-            for (int rep = 0; rep < 3; ++rep) {
-                uint64_t cnt = 0;
-                const auto t0 = std::chrono::steady_clock::now();
-                const rr_status s = draw_pipeline(P, false, 0x7u, 0, N, RR_MODE_QUANTILE, q, prec, keys, M, nullptr,
-                                                  cap, &cnt, st, &t);
-                const double dt =
-                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                if (s != RR_OK) {
-                    ms = INFINITY;
-                    break;
-                }
-                if (rep > 0) ms = std::min(ms, dt);   // the first run warms caches and code
-            }
+            const double ms = time_pool(t, N, keys, M, cap);
             if (ms < best_ms) {
                 best_ms = ms;
                 best = t;
             }
         }
+    }
+    if (std::isfinite(best_ms) && chunk_stage) {
+        double best_c = INFINITY;
+        int best_log = best.chunk_log2;
+        for (int clog = 19; clog <= 21; ++clog) {
+            Tune t = best;
+            t.chunk_log2 = clog;
+            const double ms = time_pool(t, Nc, keys, M, cap);
+            if (ms < best_c) {
+                best_c = ms;
+                best_log = clog;
+            }
+        }
+        best.chunk_log2 = best_log;
+        best_ms = std::isfinite(best_c) ? best_c : best_ms;
     }
     hipFree(keys);
     hipFree(M);
@@ -182,4 +236,42 @@ Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t
     return best;
 }
 
+bool batch_tune_lookup(int prec, int S, Tune* out) {
+    if (!tuning_enabled()) return false;
+    std::lock_guard<std::mutex> g(g_mu);
+    if (!g_loaded) load_file();
+    auto it = g_cache.find(Key(1, prec, S, -1));
+    if (it == g_cache.end()) return false;
+    Tune t = it->second.t;
+    if (!contract_db_ok(prec, S, t.db)) return false;
+    t.gen_wg = std::min(t.gen_wg, gen_wg_fit(prec, S, t.db, true));
+    *out = t;
+    return true;
+}
+
+void batch_tune_store(int prec, int S, const Tune& t, double ms) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (!g_loaded) load_file();
+    g_cache[Key(1, prec, S, -1)] = Entry{t, ms};
+    save_file();
+}
+
+std::string tune_report() {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (!g_loaded) load_file();
+    return report_json();
+}
+
 }  // namespace rr
+
+extern "C" rr_status rr_tune_report(char* buf, uint64_t len, uint64_t* needed) {
+    const std::string doc = rr::tune_report();
+    if (needed) *needed = doc.size() + 1;
+    if (!buf || len < doc.size() + 1) {
+        if (buf && len) buf[0] = 0;
+        rr::set_error("rr_tune_report: buffer too small");
+        return buf ? RR_E_CAPACITY : RR_E_ARG;
+    }
+    std::memcpy(buf, doc.c_str(), doc.size() + 1);
+    return RR_OK;
+}

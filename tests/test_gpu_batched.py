@@ -188,9 +188,20 @@ def test_autotuner_file(rr, tmp_path):
         N = 1 << 20
         keys, _, _ = rr.rr_draw_balance(P, 3, 0, N, rr.MODE_QUANTILE, 1e-4, rr.PREC_FP32)
         doc = json.loads(path.read_text())
-        ent = [e for e in doc["rr_tune"] if e["prec"] == rr.PREC_FP32 and e["S"] == 1]
-        assert ent and ent[0]["db"] in (1, 2) and ent[0]["gen_wg"] in (2, 3, 4)
+        ent = [e for e in doc["rr_tune"] if e["prec"] == rr.PREC_FP32 and e["S"] == 1 and e["batched"] == 0]
+        assert ent and ent[0]["db"] in (1, 2) and ent[0]["gen_wg"] in (2, 3, 4) and ent[0]["chunk_log2"] == 20
         say(f"  chose {ent[0]}")
+        # a call of 2^23 draws also tunes the chunk length (a new bucket: another cost)
+        X2 = inputs.gaussian_X(90, 70, 6)
+        P2 = rr.rr_prepare(dev(X2), 45, 0.0)
+        rr.rr_draw_balance(P2, 3, 0, 1 << 23, rr.MODE_QUANTILE, 1e-5, rr.PREC_FP32)
+        doc = json.loads(path.read_text())
+        rep = rr.rr_tune_report()
+        assert doc == rep, "the report and the file hold the same choices"
+        ent2 = [e for e in doc["rr_tune"] if e["prec"] == rr.PREC_FP32 and e["S"] == 1 and e["batched"] == 0
+                and e["cost_log2"] != ent[0]["cost_log2"]]
+        assert ent2 and ent2[0]["chunk_log2"] in (19, 20, 21)
+        say(f"  chose {ent2[0]}")
         # the tuned configuration gives the same pool as the oracle
         acc, _, _ = pipeline.draw_balance(X, 45, 0.0, 3, 0, 200_000, "quantile", 1e-3)
         k2, _, _ = rr.rr_draw_balance(P, 3, 0, 200_000, rr.MODE_QUANTILE, 1e-3, rr.PREC_FP32)
@@ -213,3 +224,35 @@ def test_batched_chi2_threshold(rr):
         np.testing.assert_array_equal(u64(keys), want_k)
         np.testing.assert_array_equal(M.cpu().numpy(), want_M)
         assert 0 < len(want_k) < N
+
+
+def test_batched_tuner_in_graph(rr, tmp_path):
+    """A batched call of at least 2^24 draws measures each bitmask class's tile inside the graph;
+    the choices are reported and cached, and the results equal single-pool calls."""
+    path = tmp_path / "tune_b.json"
+    os.environ["RR_TUNE_FILE"] = str(path)
+    try:
+        shapes = [(80, 12), (200, 30), (300, 50), (700, 40), (1100, 20), (60, 5), (500, 90), (260, 10)]
+        shapes = shapes * 8
+        _, Ps, seeds = _problems(rr, shapes, seed0=2400)
+        N = 1 << 18
+        say(f"batched tuner: {len(Ps)} pools x {N} draws")
+        out = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_QUANTILE, 1e-3, rr.PREC_SPLIT_BF16)
+        rep = rr.rr_tune_report()
+        classes = sorted({e["S"] for e in rep["rr_tune"] if e["batched"] == 1 and e["prec"] == rr.PREC_SPLIT_BF16})
+        want = sorted({1 if n <= 256 else 2 if n <= 512 else 4 if n <= 1024 else 8 for n, _ in shapes})
+        assert classes == want, (classes, want)
+        for e in rep["rr_tune"]:
+            if e["batched"] == 1:
+                assert e["db"] in (1, 2) and 1 <= e["gen_wg"] <= 4 and e["ms"] > 0
+                say(f"  class S={e['S']}: db {e['db']}, gen_wg {e['gen_wg']}, {e['ms']:.1f} ms")
+        if path.exists():   # written when this call probed (an earlier call may have tuned the classes)
+            assert json.loads(path.read_text()) == rep
+        # a second call uses the cached choices (no probing) and gives the same results
+        out2 = rr.rr_draw_balance_batched(Ps, seeds, 0, N, rr.MODE_QUANTILE, 1e-3, rr.PREC_SPLIT_BF16)
+        for i in range(0, len(Ps), 7):
+            keys, M, _ = rr.rr_draw_balance(Ps[i], seeds[i], 0, N, rr.MODE_QUANTILE, 1e-3, rr.PREC_SPLIT_BF16)
+            assert torch.equal(out[i][0], keys) and torch.equal(out[i][1], M)
+            assert torch.equal(out2[i][0], keys) and torch.equal(out2[i][1], M)
+    finally:
+        os.environ.pop("RR_TUNE_FILE", None)
