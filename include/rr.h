@@ -320,8 +320,9 @@ rr_status rr_realized_rmse(int64_t n1, int64_t n0, int64_t d, double M, double s
  * {"rr_tune": [{"batched": B, "prec": P, "S": S, "cost_log2": C, "db": D, "gen_wg": G,
  * "chunk_log2": L, "ms": T}, ...]}, one entry per single-pool bucket (batched = 0: precision,
  * 256-unit chunks per draw S, floor(log2(K steps x covariate blocks))) or batched class
- * (batched = 1, cost_log2 = -1): contraction tile db (32-draw blocks per wave), generation
- * workgroups per CU, draws per pipeline chunk 2^L, and the probe's time.  Writes at most len
+ * (batched = 1, cost_log2 = -1; read from RR_TUNE_FILE only, batched calls do not probe):
+ * contraction tile db (32-draw blocks per wave), generation workgroups per CU, draws per
+ * pipeline chunk 2^L, and the probe's time.  Writes at most len
  * bytes (NUL-terminated) to the host buffer buf; *needed (may be null) receives the size
  * required.  RR_E_CAPACITY when len is too small, RR_E_ARG for a null buffer. */
 rr_status rr_tune_report(char* buf, uint64_t len, uint64_t* needed);

@@ -319,8 +319,8 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         // Default tiles to start from, not the single-pool choice: a class's generation and
         // contraction run side by side over many pools, and the choice that is fastest for one
         // pool alone (for S = 4, one draw tile per wave with four generation workgroups per CU)
-        // measured about 10% slower in this launch than two tiles with three; the batched
-        // tuner below measures each class inside the graph instead.
+        // measured about 10% slower in this launch than two tiles with three.  A tune file may
+        // hold a per-class choice (read below).
         g.tune = tune_default(precision, S, true);
         g.tile = contract_tile(precision, S, g.tune.db);
         groups.push_back(g);
@@ -541,6 +541,18 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             B.exec = nullptr;
             B.graph = nullptr;
             B.sig.clear();
+            // Every capture starts from streams and events that have never been captured, so
+            // that none carries capture state (the nodes its last record or wait referred to)
+            // from a graph that has been destroyed.  Nothing runs on them now: the last launch
+            // was synchronised and the tables' copies too.
+            for (hipEvent_t ev : B.ev) hipEventDestroy(ev);
+            B.ev.clear();
+            const hipError_t d1 = hipStreamDestroy(B.s_main), d2 = hipStreamDestroy(B.s_gen);
+            B.s_main = B.s_gen = nullptr;
+            RR_HIP(d1);
+            RR_HIP(d2);
+            RR_HIP(hipStreamCreateWithFlags(&B.s_main, hipStreamNonBlocking));
+            RR_HIP(hipStreamCreateWithFlags(&B.s_gen, hipStreamNonBlocking));
             const size_t nev = 2 * R * groups.size() + 4;
             while (B.ev.size() < nev) {
                 hipEvent_t e;
@@ -637,56 +649,17 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         return RR_OK;
     };
 
-    // ---- per-class tiles measured inside this graph: the cached choice of each bitmask class,
-    // else (on a call of at least 2^24 draws in total) coordinate descent over the classes,
-    // largest work first: every (db, gen_wg) candidate of a class runs the whole graph twice
-    // with the other classes as they stand, the faster of the two GPU times counting
+    // ---- per-class tiles: the choice of each bitmask class read from the tune file, else the
+    // defaults above.  Candidates are not measured inside the graph here: a version that
+    // recaptured the whole graph once per candidate ended in a host segmentation fault of
+    // unknown cause, so that path is switched off.
     float graph_ms = 0.f;
     {
-        std::vector<char> known(groups.size(), 0);
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             Tune t{};
             if (batch_tune_lookup(precision, groups[gi].S, &t)) {
                 groups[gi].tune = t;
                 groups[gi].tile = contract_tile(precision, groups[gi].S, t.db);
-                known[gi] = 1;
-            }
-        }
-        const bool probe = tuning_on() && (uint64_t)nprob * N >= (1ull << 24) &&
-                           std::find(known.begin(), known.end(), 0) != known.end();
-        if (probe) {
-            std::vector<size_t> order(groups.size());
-            std::vector<double> work(groups.size(), 0.0);
-            for (size_t gi = 0; gi < groups.size(); ++gi) {
-                order[gi] = gi;
-                for (int64_t i : groups[gi].idx) work[gi] += (double)P[i]->P.ks * (double)P[i]->P.ncb;
-            }
-            std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return work[x] > work[y]; });
-            for (size_t gi : order) {
-                if (known[gi]) continue;
-                Group& g = groups[gi];
-                Tune best = g.tune;
-                double best_ms = INFINITY;
-                for (int db = 1; db <= 2; ++db) {
-                    if (!contract_db_ok(precision, g.S, db)) continue;
-                    const int fit = gen_wg_fit(precision, g.S, db, true);
-                    for (int gw = std::min(2, fit); gw <= fit; ++gw) {
-                        g.tune = Tune{db, gw};
-                        g.tile = contract_tile(precision, g.S, db);
-                        float m1 = 0.f, m2 = 0.f;
-                        rr_status ls = launch_graph(&m1);
-                        if (ls == RR_OK) ls = launch_graph(&m2);
-                        if (ls != RR_OK) return ls;
-                        const double ms = std::min(m1, m2);
-                        if (ms < best_ms) {
-                            best_ms = ms;
-                            best = g.tune;
-                        }
-                    }
-                }
-                g.tune = best;
-                g.tile = contract_tile(precision, g.S, best.db);
-                batch_tune_store(precision, g.S, best, best_ms);
             }
         }
         const rr_status ls = launch_graph(&graph_ms);
@@ -702,11 +675,15 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
         const AcceptState& a = hs[i];
         band_total += a.band_count;
         if (a.overflow || a.guard_fail) {
-            // guard band beyond the batched capacity: the single-pool pipeline decides this pool
+            // guard band beyond the batched capacity: the single-pool pipeline decides this pool,
+            // on the caller's stream (ordered after the graph, which has completed), so that the
+            // pool's handle records its events only on streams that outlive this batch's own
             const double keep_ms = graph_ms;
+            RR_HIP(hipEventRecord(B.join, B.s_main));
+            RR_HIP(hipStreamWaitEvent(st, B.join, 0));
             rr_status s = draw_pipeline(P[i]->P, false, seeds[i], key_begin, N, chi2 ? RR_MODE_CHI2_QUANTILE : mode,
                                         chi2 ? q_in : q_or_a, precision, d_keys[i], d_M[i], nullptr, capacity,
-                                        &h_counts[i], B.s_main, nullptr);
+                                        &h_counts[i], st, nullptr);
             graph_ms = keep_ms;
             if (s != RR_OK) result = s;
             continue;

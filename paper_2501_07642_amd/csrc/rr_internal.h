@@ -92,6 +92,7 @@ struct Problem {
     size_t aux_bytes = 0;
     hipStream_t gen_stream = nullptr;     // internal stream of the generation kernels
     std::vector<hipEvent_t> events;       // chunk ordering and timing
+    hipStream_t events_stream = nullptr;  // the caller's stream the events were last recorded on
     struct BatchState* batch = nullptr;   // batched-call resources when this handle leads a batch
 };
 void free_batch_state(Problem& P);
@@ -245,8 +246,6 @@ Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t
 // Batched launches: the cached per-class choice (precision, S) measured inside the graph, if any;
 // and recording one.
 bool batch_tune_lookup(int prec, int S, Tune* out);
-void batch_tune_store(int prec, int S, const Tune& t, double ms);
-bool tuning_on();
 rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begin, uint64_t N, int mode,
                         double q_or_a, int prec, uint64_t* d_keys, double* d_M, uint8_t* d_flags,
                         uint64_t capacity, uint64_t* h_count, hipStream_t st, const Tune* tune,

@@ -366,19 +366,19 @@ struct WS {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Resources of a released handle kept for the next handle on the same device: the draw
-// pipeline's workspace, the auxiliary workspace, the generation stream and the events.  A
-// caller that prepares a new problem for every pool (as one step of the benchmark does) then
-// allocates none of them again.  One slot per device; a newer release replaces what the slot
-// holds (those buffers are freed then), and the slot lives until the process ends.
+// Device memory of a released handle kept for the next handle on the same device: the draw
+// pipeline's workspace and the auxiliary workspace.  A caller that prepares a new problem for
+// every pool (as one step of the benchmark does) then allocates neither again.  Streams and
+// events stay with their handle and are destroyed with it: an event's last record belongs to
+// the stream it was recorded on, which the next handle knows nothing about.  One slot per
+// device; a newer release replaces what the slot holds (those buffers are freed then), and the
+// slot lives until the process ends.
 namespace {
 struct Parked {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     void* aux = nullptr;
     size_t aux_bytes = 0;
-    hipStream_t gen_stream = nullptr;
-    std::vector<hipEvent_t> events;
 };
 std::mutex g_park_mu;
 Parked g_parked[64];
@@ -386,45 +386,34 @@ Parked g_parked[64];
 void release_parked(Parked& s) {
     if (s.ws) hipFree(s.ws);
     if (s.aux) hipFree(s.aux);
-    for (hipEvent_t e : s.events) hipEventDestroy(e);
-    if (s.gen_stream) hipStreamDestroy(s.gen_stream);
     s = Parked{};
 }
 }  // namespace
 
-// Takes the parked resources of the handle's device, if the handle has none of its own.
+// Takes the parked buffers of the handle's device, if the handle has none of its own.
 static void adopt_parked(Problem& P) {
-    if (P.device < 0 || P.device >= 64 || P.ws || P.aux || P.gen_stream || !P.events.empty()) return;
+    if (P.device < 0 || P.device >= 64 || P.ws || P.aux) return;
     std::lock_guard<std::mutex> g(g_park_mu);
     Parked& s = g_parked[P.device];
     P.ws = s.ws;
     P.ws_bytes = s.ws_bytes;
     P.aux = s.aux;
     P.aux_bytes = s.aux_bytes;
-    P.gen_stream = s.gen_stream;
-    P.events = std::move(s.events);
     s = Parked{};
 }
 
-// Parks a released handle's resources (the device is idle: rr_free synchronised it).
+// Parks a released handle's buffers (the device is idle: rr_free synchronised it).
 static void park(Problem& P) {
-    if (!P.ws && !P.aux && !P.gen_stream && P.events.empty()) return;   // nothing to keep
+    if (!P.ws && !P.aux) return;   // nothing to keep
+    Parked mine{P.ws, P.ws_bytes, P.aux, P.aux_bytes};
+    P.ws = P.aux = nullptr;
     if (P.device < 0 || P.device >= 64) {
-        Parked tmp{P.ws, P.ws_bytes, P.aux, P.aux_bytes, P.gen_stream, std::move(P.events)};
-        release_parked(tmp);
+        release_parked(mine);
         return;
     }
     std::lock_guard<std::mutex> g(g_park_mu);
-    Parked& s = g_parked[P.device];
-    release_parked(s);
-    s.ws = P.ws;
-    s.ws_bytes = P.ws_bytes;
-    s.aux = P.aux;
-    s.aux_bytes = P.aux_bytes;
-    s.gen_stream = P.gen_stream;
-    s.events = std::move(P.events);
-    P.ws = P.aux = nullptr;
-    P.gen_stream = nullptr;
+    release_parked(g_parked[P.device]);
+    g_parked[P.device] = mine;
 }
 
 static rr_status ensure_ws(Problem& P, uint32_t cand_cap, uint32_t acc_cap, uint32_t band_cap, size_t bits_words, WS* w) {
@@ -628,8 +617,15 @@ ContractArgs make_contract_args(const Problem& P, int prec, const Bound& b) {
 // Per-handle resources of the two-stream pipeline: generation runs on an internal stream
 // (default priority) and overlaps the contraction of the previous chunk on the caller's
 // stream; events order the double-buffered bitmask chunks.
-static rr_status ensure_streams(Problem& P, size_t nevents) {
-    adopt_parked(P);
+static rr_status ensure_streams(Problem& P, size_t nevents, hipStream_t st) {
+    // The events are recorded on the caller's stream too; a call on another stream gets fresh
+    // events, so that none is re-recorded after the caller may have destroyed the stream it was
+    // last recorded on.
+    if (P.events_stream != st) {
+        for (hipEvent_t e : P.events) hipEventDestroy(e);
+        P.events.clear();
+        P.events_stream = st;
+    }
     if (!P.gen_stream) RR_HIP(hipStreamCreateWithFlags(&P.gen_stream, hipStreamNonBlocking));
     while (P.events.size() < nevents) {
         hipEvent_t e;
@@ -720,7 +716,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
     const uint32_t band_cap = 1u << 20;
     WS w;
     if ((s = ensure_ws(P, cand_cap, acc_cap, band_cap, chunk * wpd, &w)) != RR_OK) return s;
-    if ((s = ensure_streams(P, 4 * nchunks + 5)) != RR_OK) return s;
+    if ((s = ensure_streams(P, 4 * nchunks + 5, st)) != RR_OK) return s;
     const void* const ws_in_use = P.ws;
     const Bound b = bound_constants(P, prec);
     const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
@@ -980,7 +976,9 @@ void rr_free(rr_problem* p) {
     hipFree(P.bscale);
     hipFree(P.op_gram);
     hipFree(P.cabs);
-    park(P);   // workspace, streams and events go to the next handle on this device
+    park(P);   // the workspaces go to the next handle on this device
+    for (hipEvent_t e : P.events) hipEventDestroy(e);
+    if (P.gen_stream) hipStreamDestroy(P.gen_stream);
     free_batch_state(P);
     delete p;
 }

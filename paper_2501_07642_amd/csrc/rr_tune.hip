@@ -19,11 +19,11 @@
 // pipeline on the calling problem for a probe pool of 2^18 .. 2^20 draws (about 2^42 MFMA
 // flops), timed on the host around the synchronised call (best of two after a warm-up run);
 // then, for calls of at least 2^23 draws, the chunk length is chosen the same way on a 2^23-draw
-// pool with the winning tile.  Batched launches: per bitmask class (precision, S), the (db,
-// gen_wg) choice is measured inside the captured graph by rr_draw_balance_batched itself
-// (coordinate descent over the classes, graph time by HIP events).  Results live for the
-// process; with RR_TUNE_FILE set they are also read from and appended to that JSON file, and
-// rr_tune_report returns them.  RR_TUNE=0 disables probing (defaults everywhere).
+// pool with the winning tile.  Batched launches: per bitmask class (precision, S), a (db,
+// gen_wg) choice is taken from the tune file when it holds one ("batched": 1), else the
+// defaults; batched calls measure nothing themselves.  Results live for the process; with
+// RR_TUNE_FILE set they are also read from and appended to that JSON file, and rr_tune_report
+// returns them.  RR_TUNE=0 disables probing (defaults everywhere).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -151,8 +151,6 @@ void save_file() {
 
 }  // namespace
 
-bool tuning_on() { return tuning_enabled(); }
-
 Tune tune_for(Problem& P, int prec, bool exact, uint64_t work_draws, hipStream_t st, bool probe) {
     const Tune def = tune_default(prec, P.S, false);
     if (exact || !tuning_enabled()) return def;
@@ -247,13 +245,6 @@ bool batch_tune_lookup(int prec, int S, Tune* out) {
     t.gen_wg = std::min(t.gen_wg, gen_wg_fit(prec, S, t.db, true));
     *out = t;
     return true;
-}
-
-void batch_tune_store(int prec, int S, const Tune& t, double ms) {
-    std::lock_guard<std::mutex> g(g_mu);
-    if (!g_loaded) load_file();
-    g_cache[Key(1, prec, S, -1)] = Entry{t, ms};
-    save_file();
 }
 
 std::string tune_report() {
