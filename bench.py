@@ -20,6 +20,7 @@ each kernel on its own.
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -39,9 +40,10 @@ CONTRACT_SRC = os.path.join(ROOT, "paper_2501_07642_amd", "csrc", "rr_contract.h
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_traffic_stream_n1000_d1000.md")
 
 
-def measured_traffic():
+def measured_traffic(draws_per_launch):
     """HBM bytes per contraction launch from the committed PMC summary, or None when the
-    summary is missing or was taken on a different contraction source."""
+    summary is missing, was taken on a different contraction source, or on launches of another
+    length than this run's full chunks (the autotuner picks the chunk per box)."""
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
@@ -56,6 +58,8 @@ def measured_traffic():
     if fields.get("contract_source_sha256") != src:
         return None
     try:
+        if int(fields["draws_per_launch"]) != int(draws_per_launch):
+            return None
         return float(fields["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -281,14 +285,16 @@ def main():
     issued_per_draw = 4.0 * n * (n if gram else d)
     launches_per_step = launches / args.steps
     avg_launch_ms = contract_ms / max(launches, 1)
+    # full chunk length of this run's launches (a power of two; the last chunk of a pool is short)
+    full_chunk = 1 << int(round(math.log2(N / max(launches_per_step, 1))))
     achieved = alg_flops_per_draw * N * args.steps / (contract_ms / 1000.0) / 1e12
     issued = issued_per_draw * N * args.steps / (contract_ms / 1000.0) / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None if gram else measured_traffic(),
+                "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None if gram else measured_traffic(full_chunk),
                 "kernel": ("contract_kernel<Gram BF16> (W K on 32x32x16 BF16 MFMA + w^T (W K) + prefilter)" if gram else
                            "contract_kernel<split BF16> (W X~ on 32x32x16 BF16 MFMA + reduce + prefilter)"),
                 "avg_launch_ms": avg_launch_ms, "launches_per_step": launches_per_step,
-                "draws_per_launch": N / max(launches_per_step, 1),
+                "draws_per_launch": N / max(launches_per_step, 1), "full_chunk_draws": full_chunk,
                 "algorithmic_flops_per_draw": alg_flops_per_draw,
                 "issued_mfma_flops_per_draw": issued_per_draw, "issued_mfma_tflops": issued,
                 "issued_mfma_frac": issued / PEAK_BF16_TFLOPS,
@@ -311,6 +317,8 @@ def main():
     fp32 = None
     if not args.no_fp32 and not gram:
         P = rr.rr_prepare(Xd, n1, w["ridge_rel"])
+        # untimed first call of the FP32 bucket: the autotuner probes its candidates there
+        rr.rr_draw_balance(P, w["seed"], w["key_begin"], min(N, 1 << 23), rr.MODE_QUANTILE, q, rr.PREC_FP32)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         keys32, _, _ = rr.rr_draw_balance(P, w["seed"], w["key_begin"], N, rr.MODE_QUANTILE, q, rr.PREC_FP32)
