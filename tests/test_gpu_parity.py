@@ -130,6 +130,22 @@ def test_pool_small(rr, prec, mode, qa):
     say(f"  accepted {len(got)} band {t['band']}")
 
 
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8", "gram"])
+@pytest.mark.parametrize("mode,qa", [("quantile", 1.0), ("threshold", float("inf")), ("threshold", 0.0),
+                                     ("threshold", -1.0)])
+def test_pool_accept_all_or_none(rr, prec, mode, qa):
+    """Degenerate acceptance: q = 1 and an infinite threshold keep every draw (in key order), a
+    threshold at or below zero keeps none (M >= 0), as in the oracle."""
+    say(f"pool accept all or none {mode} {qa} {prec}")
+    X = inputs.gaussian_X(60, 8, 5)
+    _, got, t = _check_pool(rr, X, 30, 0.0, 4242, 1500, mode, qa, prec)
+    keep_all = mode == "quantile" or qa == float("inf")
+    assert len(got) == (1500 if keep_all else 0)
+    if keep_all:
+        np.testing.assert_array_equal(got, np.arange(1500, dtype=np.uint64))
+    say(f"  accepted {len(got)} band {t['band']}")
+
+
 def test_pool_ragged_tiles(rr):
     # draw counts that leave partial tiles; n not a multiple of 16 / 32 / 64
     for n, d, N in [(37, 5, 1), (37, 5, 63), (101, 33, 129), (531, 70, 1000)]:
