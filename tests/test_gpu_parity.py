@@ -312,6 +312,18 @@ def test_high_dim_diagonal_pool(rr, prec):
 
 
 @pytest.mark.parametrize("prec", ["split", "fp32", "i8", "gram"])
+@pytest.mark.parametrize("n,d", [(60, 59), (60, 80)])
+def test_pool_d_at_least_n_minus_1(rr, prec, n, d):
+    """Whitened metric with d >= n - 1 (ridge 1e-3): M is nearly the same for every draw, so FP32
+    cannot order the draws and most of them go through the FP64 guard band; the accepted set is
+    still the oracle's."""
+    say(f"pool d >= n - 1: n={n} d={d} {prec}")
+    X = inputs.gaussian_X(n, d, 11 * d)
+    _, got, t = _check_pool(rr, X, n // 2, 1e-3, 31, 5000, "quantile", 0.02, prec)
+    say(f"  accepted {len(got)} band {t['band']}")
+
+
+@pytest.mark.parametrize("prec", ["split", "fp32", "i8", "gram"])
 def test_pool_extreme_n1(rr, prec):
     """One treated unit, and one control unit, in every operand form."""
     X = inputs.gaussian_X(97, 6, 977)
