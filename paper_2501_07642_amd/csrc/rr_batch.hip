@@ -545,14 +545,23 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             // that none carries capture state (the nodes its last record or wait referred to)
             // from a graph that has been destroyed.  Nothing runs on them now: the last launch
             // was synchronised and the tables' copies too.
+            // The timing and ordering events were last recorded on the old streams: they are
+            // replaced with them, so that no event is re-recorded after its stream is gone.
             for (hipEvent_t ev : B.ev) hipEventDestroy(ev);
             B.ev.clear();
+            for (hipEvent_t* ev : {&B.t0, &B.t1, &B.join}) {
+                if (*ev) hipEventDestroy(*ev);
+                *ev = nullptr;
+            }
             const hipError_t d1 = hipStreamDestroy(B.s_main), d2 = hipStreamDestroy(B.s_gen);
             B.s_main = B.s_gen = nullptr;
             RR_HIP(d1);
             RR_HIP(d2);
             RR_HIP(hipStreamCreateWithFlags(&B.s_main, hipStreamNonBlocking));
             RR_HIP(hipStreamCreateWithFlags(&B.s_gen, hipStreamNonBlocking));
+            RR_HIP(hipEventCreate(&B.t0));
+            RR_HIP(hipEventCreate(&B.t1));
+            RR_HIP(hipEventCreateWithFlags(&B.join, hipEventDisableTiming));
             const size_t nev = 2 * R * groups.size() + 4;
             while (B.ev.size() < nev) {
                 hipEvent_t e;

@@ -184,32 +184,38 @@ def test_batched_512_against_oracle_pools(rr):
 
 
 def test_autotuner_file(rr, tmp_path):
-    """A call large enough to tune writes its bucket's choice to RR_TUNE_FILE."""
+    """A call large enough to tune writes its bucket's choice to RR_TUNE_FILE.  The buckets
+    (precision, 256-unit chunks S, log2 of K steps x covariate blocks) are ones no earlier test
+    tunes: FP32 at n = 200 with 2 and with 8 covariate blocks (the streaming pool of n = 64,
+    d = 8 tunes FP32 at 8 K steps x 2 blocks)."""
     path = tmp_path / "tune.json"
     os.environ["RR_TUNE_FILE"] = str(path)
     try:
-        say("autotuner: fp32, n=90, d=7, 2^20 draws")
-        X = inputs.gaussian_X(90, 7, 5)
-        P = rr.rr_prepare(dev(X), 45, 0.0)
+        before = {(e["prec"], e["S"], e["cost_log2"]) for e in rr.rr_tune_report()["rr_tune"] if e["batched"] == 0}
+        assert (rr.PREC_FP32, 1, 5) not in before and (rr.PREC_FP32, 1, 6) not in before, before
+        say("autotuner: fp32, n=200, d=7, 2^20 draws")
+        X = inputs.gaussian_X(200, 7, 5)
+        P = rr.rr_prepare(dev(X), 100, 0.0)
         N = 1 << 20
         keys, _, _ = rr.rr_draw_balance(P, 3, 0, N, rr.MODE_QUANTILE, 1e-4, rr.PREC_FP32)
         doc = json.loads(path.read_text())
-        ent = [e for e in doc["rr_tune"] if e["prec"] == rr.PREC_FP32 and e["S"] == 1 and e["batched"] == 0]
+        ent = [e for e in doc["rr_tune"] if e["prec"] == rr.PREC_FP32 and e["S"] == 1 and e["batched"] == 0
+               and e["cost_log2"] == 5]
         assert ent and ent[0]["db"] in (1, 2) and ent[0]["gen_wg"] in (2, 3, 4) and ent[0]["chunk_log2"] == 20
         say(f"  chose {ent[0]}")
-        # a call of 2^23 draws also tunes the chunk length (a new bucket: another cost)
-        X2 = inputs.gaussian_X(90, 70, 6)
-        P2 = rr.rr_prepare(dev(X2), 45, 0.0)
+        # a call of 2^23 draws also tunes the chunk length (a new bucket: 8 covariate blocks)
+        X2 = inputs.gaussian_X(200, 100, 6)
+        P2 = rr.rr_prepare(dev(X2), 100, 0.0)
         rr.rr_draw_balance(P2, 3, 0, 1 << 23, rr.MODE_QUANTILE, 1e-5, rr.PREC_FP32)
         doc = json.loads(path.read_text())
         rep = rr.rr_tune_report()
         assert doc == rep, "the report and the file hold the same choices"
         ent2 = [e for e in doc["rr_tune"] if e["prec"] == rr.PREC_FP32 and e["S"] == 1 and e["batched"] == 0
-                and e["cost_log2"] != ent[0]["cost_log2"]]
+                and e["cost_log2"] == 6]
         assert ent2 and ent2[0]["chunk_log2"] in (19, 20, 21)
         say(f"  chose {ent2[0]}")
         # the tuned configuration gives the same pool as the oracle
-        acc, _, _ = pipeline.draw_balance(X, 45, 0.0, 3, 0, 200_000, "quantile", 1e-3)
+        acc, _, _ = pipeline.draw_balance(X, 100, 0.0, 3, 0, 200_000, "quantile", 1e-3)
         k2, _, _ = rr.rr_draw_balance(P, 3, 0, 200_000, rr.MODE_QUANTILE, 1e-3, rr.PREC_FP32)
         np.testing.assert_array_equal(u64(k2), acc)
         assert len(u64(keys)) == 105
@@ -275,7 +281,11 @@ def test_first_call_of_a_tuning_bucket_on_a_fresh_handle(rr):
     X = inputs.gaussian_X(1100, 17, 77)
     P = rr.rr_prepare(dev(X), 550, 0.0)
     N = 1 << 20
+    # the bucket (int8, S = 8, 72 K steps x 2 covariate blocks) is untuned, so this call probes
+    tuned = {(e["prec"], e["S"], e["cost_log2"]) for e in rr.rr_tune_report()["rr_tune"] if e["batched"] == 0}
+    assert (rr.PREC_FIXED_I8, 8, 7) not in tuned, tuned
     k1, M1, f1 = rr.rr_draw_balance(P, 91, 0, N, rr.MODE_QUANTILE, 1e-4, rr.PREC_FIXED_I8)
+    assert (rr.PREC_FIXED_I8, 8, 7) in {(e["prec"], e["S"], e["cost_log2"]) for e in rr.rr_tune_report()["rr_tune"]}
     k2, M2, f2 = rr.rr_draw_balance(P, 91, 0, N, rr.MODE_QUANTILE, 1e-4, rr.PREC_FIXED_I8)
     assert k1.numel() == 105 and torch.equal(k1, k2) and torch.equal(M1, M2)
     ref = pipeline.balance_of_keys(X, 550, 0.0, 91, u64(k1))
