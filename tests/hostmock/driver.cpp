@@ -241,6 +241,40 @@ int main(int argc, char** argv) {
         release(p);
     }
     {
+        // one handle used from several caller streams in turn, one of them destroyed between
+        // calls: the handle's events must never be re-recorded after their stream is gone
+        Pool p = prep(200, 100, 20);
+        hipStream_t a, b, c;
+        hipStreamCreateWithFlags(&a, hipStreamNonBlocking);
+        hipStreamCreateWithFlags(&b, hipStreamNonBlocking);
+        void *k, *M, *fl, *cnt, *st;
+        hipMalloc(&k, 8 * 60000);
+        hipMalloc(&M, 8 * 60000);
+        hipMalloc(&fl, 60000);
+        hipMalloc(&cnt, 8);
+        hipMalloc(&st, 4);
+        uint64_t hc = 0;
+        auto on = [&](hipStream_t s, bool async) {
+            return async ? rr_draw_balance_async(p.P, 9, 0, 60000, T, 5.0, RR_PREC_SPLIT_BF16,
+                                                 static_cast<uint64_t*>(k), static_cast<double*>(M),
+                                                 static_cast<uint8_t*>(fl), 60000, static_cast<uint64_t*>(cnt),
+                                                 static_cast<int32_t*>(st), s)
+                         : rr_draw_balance(p.P, 9, 0, 60000, T, 5.0, RR_PREC_SPLIT_BF16, static_cast<uint64_t*>(k),
+                                           static_cast<double*>(M), static_cast<uint8_t*>(fl), 60000, &hc, s);
+        };
+        check(on(a, true) == RR_OK && on(a, false) == RR_OK, "calls on a first stream");
+        check(on(b, false) == RR_OK, "then on a second stream");
+        hipStreamDestroy(a);
+        hipStreamCreateWithFlags(&c, hipStreamNonBlocking);
+        check(on(c, true) == RR_OK && on(b, false) == RR_OK && on(nullptr, false) == RR_OK,
+              "after the first stream is destroyed: a third stream, the second, the null stream");
+        hipStreamDestroy(b);
+        hipStreamDestroy(c);
+        for (void* q : {k, M, fl, cnt, st}) hipFree(q);
+        release(p);
+        check(true, "handle released after its streams were destroyed");
+    }
+    {
         // tuning-size calls: the autotuner probes on the calling handle before the call runs
         Pool p = prep(1100, 550, 17, 0.0);
         check(single(p, 91, 1u << 20, T, 10.0, RR_PREC_FIXED_I8, 1u << 20) == RR_OK, "first call of a tuning bucket");

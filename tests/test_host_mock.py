@@ -68,6 +68,7 @@ def test_host_logic_under_sanitizers(driver, shapes_file):
                  "replaced handle with the same arguments: a new graph",
                  "the next handle's first call reuses the released workspace",
                  "allocation-free entry point allocates and frees nothing",
+                 "after the first stream is destroyed: a third stream, the second, the null stream",
                  "the 512-pool workload"):
         assert f"CHECK {name} ok" in out
 
