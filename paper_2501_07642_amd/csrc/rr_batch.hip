@@ -543,10 +543,10 @@ extern "C" rr_status rr_draw_balance_batched(rr_problem* const* P, int64_t nprob
             B.sig.clear();
             // Every capture starts from streams and events that have never been captured, so
             // that none carries capture state (the nodes its last record or wait referred to)
-            // from a graph that has been destroyed.  Nothing runs on them now: the last launch
-            // was synchronised and the tables' copies too.
-            // The timing and ordering events were last recorded on the old streams: they are
-            // replaced with them, so that no event is re-recorded after its stream is gone.
+            // from a graph that has been destroyed; the timing and ordering events recorded
+            // outside the graph go with the old streams too, so that no event is re-recorded
+            // after its stream is gone.  Nothing runs on the old ones now: the last launch was
+            // synchronised, and so were the tables' copies.
             for (hipEvent_t ev : B.ev) hipEventDestroy(ev);
             B.ev.clear();
             for (hipEvent_t* ev : {&B.t0, &B.t1, &B.join}) {
