@@ -277,6 +277,13 @@ def main():
     ms_per_step = 1000.0 * elapsed / args.steps
     value = N / (ms_per_step / 1000.0)
     keys_split = keys_s.cpu().numpy()
+    # error of the FP32 balance values against FP64 on the accepted draws (outside the timed
+    # region): both device paths on the same keys, with the rigorous bound of each draw
+    m32, err32, m64 = rr.rr_balance_keys(P, w["seed"], keys_s, main_prec)
+    m32n, errn, m64n = (x.cpu().numpy().astype(np.float64) for x in (m32, err32, m64))
+    m_err = {"draws": int(len(m64n)), "max_rel_err": float(np.max(np.abs(m32n - m64n) / m64n)),
+             "max_err_over_bound": float(np.max(np.abs(m32n - m64n) / errn)),
+             "median_bound_rel": float(np.median(errn / m64n))} if len(m64n) else None
 
     # Algorithmic work of one balance check (the method, not the dense form): the treated sum
     # G = sum_{i in T} X~_i is n1 d additions, and ||G||^2 is d multiply-adds.  The dense form
@@ -368,7 +375,7 @@ def main():
                    "metric": w.get("metric", "mahalanobis"),
                    "step": "rr_prepare + rr_draw_balance + rr_rand_test(201 nulls)"},
         "roofline": roofline, "cpu_baseline": base, "fp32_form": fp32, "i8_form": i8, "split_form": split,
-        "contract_kernel_ms_per_step": contract_ms / args.steps, "guard_band": band,
+        "contract_kernel_ms_per_step": contract_ms / args.steps, "guard_band": band, "m32_vs_fp64": m_err,
         "rand_test_counts_min": int(counts.min().item()) if counts is not None else None,
         "tuner": [e for e in rr.rr_tune_report()["rr_tune"] if e["batched"] == 0],
     }
