@@ -9,8 +9,8 @@
 // [32 DB w, 32 DB (w+1)).  G^T = X~^T W^T is computed per covariate chunk of 32 CB: the A
 // operand (32 covariates x 16 units of X~^T) comes from the precomputed operand records,
 // staged from global memory straight into LDS eight K steps at a time (double-buffered,
-// shared by the waves of the workgroup);
-// the B operand (16 units x 32 draws of W^T) is expanded from the tile's bitmasks in LDS.
+// shared by the waves of the workgroup; the barrier that hands a stage over sits before its
+// last K step in the MFMA-16 forms); the B operand (16 units x 32 draws of W^T) is expanded from the tile's bitmasks in LDS.
 // In an output block, lane l holds draw l % 32 and 16 covariates, so ||G||^2 is reduced in
 // registers and across the two lane halves; the error bounds need only ||G|| (or, for the
 // Gram form, the sum of |G'_j| over the treated units).  For the per-column criterion
@@ -71,6 +71,12 @@ template <int PREC, int NW, int CB, int DB, int S, bool BATCH>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 3 : NW / 2)))
 void contract_kernel(ContractArgs a0) {
     constexpr int TILE = NW * 32 * DB;
+    // Stage barrier of the one-plane and two-plane MFMA forms: it sits before the last K step of
+    // a stage, whose operands are then already in registers, so that the waves of a SIMD, which
+    // leave every barrier together, restart on those MFMAs rather than on LDS reads; the copy of
+    // stage gs + 2 into the buffer stage gs has left follows them.  (The FP32 form keeps the
+    // barrier at the end of the stage.)
+    constexpr bool kEarly = PREC != RR_PREC_FP32;
     constexpr int WSTR = 8 * S + 1;                       // +1: 32 draws hit 32 banks
     constexpr bool kGram = PREC == RR_PREC_GRAM_BF16;
     constexpr bool kSplitLike = PREC == RR_PREC_SPLIT_BF16 || kGram;
@@ -121,8 +127,17 @@ void contract_kernel(ContractArgs a0) {
             sbits[dr * WSTR + w] = idx < a.num ? __builtin_nontemporal_load(a.bits + idx * (8 * S) + w) : 0u;
         }
         issue_stage(0, 0);
+        if (kEarly && total > 1) issue_stage(1, 1);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        // before the last K step of stage gs: the copy of stage gs + 1 has landed for every wave,
+        // and no wave reads buffer gs & 1 any more (the last step's operands are in registers)
+        auto early_barrier = [&]() {
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            __builtin_amdgcn_sched_barrier(0);
+        };
 
         float ss[DB], ssa[DB];
 #pragma unroll
@@ -141,7 +156,7 @@ void contract_kernel(ContractArgs a0) {
 #pragma unroll
                         for (int e = 0; e < 16; ++e) acc[cb][db][e] = 0;
             }
-            if (gs + 1 < total) issue_stage(gs + 1, (gs + 1) & 1);
+            if (!kEarly && gs + 1 < total) issue_stage(gs + 1, (gs + 1) & 1);
             const uint4* st = sA + (gs & 1) * STAGE_U4;
             // bitmask words of this stage: units 128 kst .. 128 kst + 127
             uint32_t wd[DB][kKStage / 2];
@@ -182,6 +197,7 @@ void contract_kernel(ContractArgs a0) {
 #pragma unroll
                         for (int p = 0; p < 2; ++p)
                             A[cb][p] = __builtin_bit_cast(bf16x8, st[((kk * CB + cb) * 2 + p) * 64 + lane]);
+                    if (kk == kKStage - 1) early_barrier();
 #pragma unroll
                     for (int g = 0; g < 2 * CB; ++g) {
                         const int cb = g >> 1, p = g & 1;
@@ -213,6 +229,7 @@ void contract_kernel(ContractArgs a0) {
                     i32x4 A[CB];
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb) A[cb] = __builtin_bit_cast(i32x4, st[(kk * CB + cb) * 64 + lane]);
+                    if (kk == kKStage - 1) early_barrier();
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb) {
                         __builtin_amdgcn_sched_barrier(0);
@@ -260,6 +277,7 @@ void contract_kernel(ContractArgs a0) {
                     }
                 }
             }
+            if (kEarly && gs + 2 < total) issue_stage(gs + 2, gs & 1);   // buffer gs & 1 is free
             if (kst == nst - 1) {
                 // ||G||^2 over this chunk's covariates
 #pragma unroll
@@ -312,9 +330,12 @@ void contract_kernel(ContractArgs a0) {
                     if constexpr (kGram) ssa[db] += sa;
                 }
             }
-            __builtin_amdgcn_s_waitcnt(0);     // this wave's loads of the next stage landed
-            __syncthreads();
+            if constexpr (!kEarly) {
+                __builtin_amdgcn_s_waitcnt(0);     // this wave's loads of the next stage landed
+                __syncthreads();
+            }
         }
+        if constexpr (kEarly) __syncthreads();   // every wave done with this tile's LDS before the next tile's
 
 #pragma unroll
         for (int db = 0; db < DB; ++db) {
