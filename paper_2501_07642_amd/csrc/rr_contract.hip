@@ -65,6 +65,8 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 constexpr int planes_for(int prec) { return prec == RR_PREC_FIXED_I8 ? 1 : 2; }
 
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 template <int PREC, int NW, int CB, int DB, int S, bool BATCH>
 // 8-wave tiles: at most 168 registers per wave (two waves per SIMD, 336 of the 512 registers),
 // which leaves three 64-register generation waves per SIMD beside them.
@@ -108,16 +110,24 @@ void contract_kernel(ContractArgs a0) {
         const int nst = a.ks / kKStage;          // ks is a multiple of kKStage
         const int total = nchunks * nst;
 
-        // Stage gs = (chunk, K stage) goes straight from global memory to LDS buffer `buf`;
-        // wave w moves plane records w, w + NW, ... (64 lanes x 16 B each).
-        auto issue_stage = [&](int gs, int buf) {
-            const int chunk = gs / nst, kst = gs % nst;
+        // Stage (chunk, K stage) goes straight from global memory to LDS buffer `buf`; wave w
+        // moves plane records w, w + NW, ... (64 lanes x 16 B each).  The records' offsets
+        // within a stage are fixed per tile; a stage adds one wave-uniform base.
+        constexpr int NREC = REC / NW;
+        const int wv = uniform_int(wave);
+        uint32_t roff[NREC];
 #pragma unroll
-            for (int r = wave; r < REC; r += NW) {
-                const int kk = r / (CB * PL), cb = (r / PL) % CB, p = r % PL;
-                const int k = kst * kKStage + kk;
-                const uint4* src = a.op + ((size_t)k * a.ncb + chunk * CB + cb) * RECU4 + 64 * p + lane;
-                __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(sA + buf * STAGE_U4 + r * 64), 16, 0, 0);
+        for (int i = 0; i < NREC; ++i) {
+            const int r = wv + i * NW;
+            const int kk = r / (CB * PL), cb = (r / PL) % CB, p = r % PL;
+            roff[i] = (uint32_t)((kk * a.ncb + cb) * RECU4 + 64 * p + lane);
+        }
+        auto issue_stage = [&](int chunk, int kst, int buf) {
+            const uint4* base = a.op + ((size_t)kst * kKStage * a.ncb + (size_t)chunk * CB) * RECU4;
+#pragma unroll
+            for (int i = 0; i < NREC; ++i) {
+                const uint4* src = base + roff[i];
+                __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(sA + buf * STAGE_U4 + (wv + i * NW) * 64), 16, 0, 0);
             }
         };
         if (tile0 >= a.num) continue;
@@ -126,8 +136,8 @@ void contract_kernel(ContractArgs a0) {
             const uint64_t idx = tile0 + dr;
             sbits[dr * WSTR + w] = idx < a.num ? __builtin_nontemporal_load(a.bits + idx * (8 * S) + w) : 0u;
         }
-        issue_stage(0, 0);
-        if (kEarly && total > 1) issue_stage(1, 1);
+        issue_stage(0, 0, 0);
+        if (kEarly && total > 1) issue_stage(nst > 1 ? 0 : 1, nst > 1 ? 1 : 0, 1);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         // before the last K step of stage gs: the copy of stage gs + 1 has landed for every wave,
@@ -146,8 +156,11 @@ void contract_kernel(ContractArgs a0) {
         AccT acc[CB][DB];
         const uint32_t* myb = sbits + (wave * 32 * DB + j) * WSTR;
 
+        // (chunk, K stage) of the stage being computed and of the stage two ahead, advanced by one
+        // stage per iteration
+        int chunk = 0, kst = 0;
+        int chunk2 = nst > 2 ? 0 : (nst == 2 ? 1 : 2), kst2 = nst > 2 ? 2 : 0;
         for (int gs = 0; gs < total; ++gs) {
-            const int chunk = gs / nst, kst = gs % nst;
             if (kst == 0) {
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb)
@@ -156,7 +169,7 @@ void contract_kernel(ContractArgs a0) {
 #pragma unroll
                         for (int e = 0; e < 16; ++e) acc[cb][db][e] = 0;
             }
-            if (!kEarly && gs + 1 < total) issue_stage(gs + 1, (gs + 1) & 1);
+            if (!kEarly && gs + 1 < total) issue_stage(kst + 1 < nst ? chunk : chunk + 1, kst + 1 < nst ? kst + 1 : 0, (gs + 1) & 1);
             const uint4* st = sA + (gs & 1) * STAGE_U4;
             // bitmask words of this stage: units 128 kst .. 128 kst + 127
             uint32_t wd[DB][kKStage / 2];
@@ -165,6 +178,12 @@ void contract_kernel(ContractArgs a0) {
 #pragma unroll
                 for (int q = 0; q < kKStage / 2; ++q) wd[db][q] = myb[32 * db * WSTR + (kKStage / 2) * kst + q];
             if constexpr (kSplitLike) {
+                // the first K step's operands are read before the B expansion waits on the bits
+                bf16x8 A0[CB][2];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) A0[cb][p] = __builtin_bit_cast(bf16x8, st[(cb * 2 + p) * 64 + lane]);
                 // Software pipeline: the B fragments of step kk + 1 are expanded between the
                 // MFMA groups of step kk (scheduling fences keep that order).
                 uint32_t wr[DB][kKStage / 2];
@@ -196,7 +215,8 @@ void contract_kernel(ContractArgs a0) {
                     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
                         for (int p = 0; p < 2; ++p)
-                            A[cb][p] = __builtin_bit_cast(bf16x8, st[((kk * CB + cb) * 2 + p) * 64 + lane]);
+                            A[cb][p] = kk == 0 ? A0[cb][p]
+                                               : __builtin_bit_cast(bf16x8, st[((kk * CB + cb) * 2 + p) * 64 + lane]);
                     if (kk == kKStage - 1) early_barrier();
 #pragma unroll
                     for (int g = 0; g < 2 * CB; ++g) {
@@ -277,7 +297,7 @@ void contract_kernel(ContractArgs a0) {
                     }
                 }
             }
-            if (kEarly && gs + 2 < total) issue_stage(gs + 2, gs & 1);   // buffer gs & 1 is free
+            if (kEarly && gs + 2 < total) issue_stage(chunk2, kst2, gs & 1);   // buffer gs & 1 is free
             if (kst == nst - 1) {
                 // ||G||^2 over this chunk's covariates
 #pragma unroll
@@ -333,6 +353,14 @@ void contract_kernel(ContractArgs a0) {
             if constexpr (!kEarly) {
                 __builtin_amdgcn_s_waitcnt(0);     // this wave's loads of the next stage landed
                 __syncthreads();
+            }
+            if (++kst == nst) {
+                kst = 0;
+                ++chunk;
+            }
+            if (++kst2 == nst) {
+                kst2 = 0;
+                ++chunk2;
             }
         }
         if constexpr (kEarly) __syncthreads();   // every wave done with this tile's LDS before the next tile's
