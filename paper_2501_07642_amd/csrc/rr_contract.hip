@@ -160,6 +160,14 @@ void contract_kernel(ContractArgs a0) {
         // stage per iteration
         int chunk = 0, kst = 0;
         int chunk2 = nst > 2 ? 0 : (nst == 2 ? 1 : 2), kst2 = nst > 2 ? 2 : 0;
+        // split forms: A fragments of the step about to run, carried across stages
+        bf16x8 Acur[CB][2];
+        if constexpr (kSplitLike) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int p = 0; p < 2; ++p) Acur[cb][p] = __builtin_bit_cast(bf16x8, sA[(cb * 2 + p) * 64 + lane]);
+        }
         for (int gs = 0; gs < total; ++gs) {
             if (kst == 0) {
 #pragma unroll
@@ -178,12 +186,6 @@ void contract_kernel(ContractArgs a0) {
 #pragma unroll
                 for (int q = 0; q < kKStage / 2; ++q) wd[db][q] = myb[32 * db * WSTR + (kKStage / 2) * kst + q];
             if constexpr (kSplitLike) {
-                // the first K step's operands are read before the B expansion waits on the bits
-                bf16x8 A0[CB][2];
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                    for (int p = 0; p < 2; ++p) A0[cb][p] = __builtin_bit_cast(bf16x8, st[(cb * 2 + p) * 64 + lane]);
                 // Software pipeline: the B fragments of step kk + 1 are expanded between the
                 // MFMA groups of step kk (scheduling fences keep that order).
                 uint32_t wr[DB][kKStage / 2];
@@ -207,28 +209,35 @@ void contract_kernel(ContractArgs a0) {
                 bf16x8 Bc[DB], Bn[DB];
 #pragma unroll
                 for (int db = 0; db < DB; ++db) Bc[db] = expand(0, db);
+                // The A fragments of step kk + 1 are read during step kk, one per MFMA group; those
+                // of the next stage's first step are read in the last step, after the barrier that
+                // makes that stage's buffer complete (after a tile's last stage the read is of a
+                // stale buffer and unused).
+                const uint4* stn = sA + ((gs + 1) & 1) * STAGE_U4;
 #pragma unroll
                 for (int kk = 0; kk < kKStage; ++kk) {
                     const bool more = kk + 1 < kKStage;
-                    bf16x8 A[CB][2];
-#pragma unroll
-                    for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                        for (int p = 0; p < 2; ++p)
-                            A[cb][p] = kk == 0 ? A0[cb][p]
-                                               : __builtin_bit_cast(bf16x8, st[((kk * CB + cb) * 2 + p) * 64 + lane]);
                     if (kk == kKStage - 1) early_barrier();
+                    bf16x8 An[CB][2];
 #pragma unroll
                     for (int g = 0; g < 2 * CB; ++g) {
                         const int cb = g >> 1, p = g & 1;
                         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                         for (int db = 0; db < DB; ++db)
-                            acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[cb][p], Bc[db], acc[cb][db], 0, 0, 0);
+                            acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Acur[cb][p], Bc[db], acc[cb][db], 0, 0, 0);
                         __builtin_amdgcn_sched_barrier(0);
+                        if (more)
+                            An[cb][p] = __builtin_bit_cast(bf16x8, st[(((kk + 1) * CB + cb) * 2 + p) * 64 + lane]);
+                        else
+                            An[cb][p] = __builtin_bit_cast(bf16x8, stn[(cb * 2 + p) * 64 + lane]);
                         if (more && g < DB) Bn[g] = expand(kk + 1, g);
                     }
                     __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                        for (int p = 0; p < 2; ++p) Acur[cb][p] = An[cb][p];
                     if (more) {
 #pragma unroll
                         for (int db = 0; db < DB; ++db) Bc[db] = Bn[db];
