@@ -24,18 +24,42 @@ namespace rr {
 
 constexpr int kNB = 32;   // Cholesky / solve block
 
-__global__ void mean_center_kernel(const void* X, int fp32, int64_t n, int64_t d, int64_t ldx,
-                                   double* mu, double* Xc) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= d) return;
-    double s = 0.0;
-    for (int64_t i = 0; i < n; ++i)
-        s += fp32 ? (double)((const float*)X)[i * ldx + j] : ((const double*)X)[i * ldx + j];
-    const double m = s / (double)n;
-    mu[j] = m;
-    for (int64_t i = 0; i < n; ++i) {
-        const double x = fp32 ? (double)((const float*)X)[i * ldx + j] : ((const double*)X)[i * ldx + j];
-        Xc[i * d + j] = x - m;
+// Per-column reductions over the n units: one workgroup of kRowW waves per kColW columns, wave
+// w summing units w, w + kRowW, ... of its lane's column; the kRowW partial results are then
+// added in wave order, so every sum has one fixed order.
+constexpr int kColW = 64, kRowW = 16;
+
+template <int K>
+__device__ __forceinline__ void combine_rows(double (*part)[kRowW][kColW], const double (&v)[K], double (&out)[K]) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) part[q][w][l] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double t = 0.0;
+        for (int r = 0; r < kRowW; ++r) t += part[q][r][l];
+        out[q] = t;
+    }
+}
+
+// Column means mu and the centred copy Xc = X - 1 mu^T (FP64), X of either precision.
+__global__ __launch_bounds__(kColW * kRowW) void mean_center_kernel(const void* X, int fp32, int64_t n, int64_t d,
+                                                                     int64_t ldx, double* mu, double* Xc) {
+    __shared__ double part[1][kRowW][kColW];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * kColW + l;
+    auto x = [&](int64_t i) {
+        return fp32 ? (double)((const float*)X)[i * ldx + j] : ((const double*)X)[i * ldx + j];
+    };
+    double v[1] = {0.0}, t[1];
+    if (j < d)
+        for (int64_t i = w; i < n; i += kRowW) v[0] += x(i);
+    combine_rows<1>(part, v, t);
+    const double m = t[0] / (double)n;
+    if (j < d) {
+        if (w == 0) mu[j] = m;
+        for (int64_t i = w; i < n; i += kRowW) Xc[i * d + j] = x(i) - m;
     }
 }
 
@@ -281,30 +305,40 @@ __global__ void operands_i8_kernel(const double* X, int64_t n, int64_t d, int64_
 
 // e_j = max(sum of the positive, sum of the negative parts of s q_ij - x_ij) over all units
 // bounds |sum_{i in T} (s q_ij - x_ij)| for every treated set T; FP64, widened by 1e-12.
-__global__ void qerr_kernel(const double* X, int64_t n, int64_t d, const float* bscale, double* e) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= d) return;
-    const float s = bscale[j / 32];
-    double pos = 0.0, neg = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        const double x = X[i * d + j];
-        const double r = (double)s * (double)quantise(x, s) - x;
-        if (r > 0) pos += r; else neg -= r;
+__global__ __launch_bounds__(kColW * kRowW) void qerr_kernel(const double* X, int64_t n, int64_t d,
+                                                              const float* bscale, double* e) {
+    __shared__ double part[2][kRowW][kColW];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * kColW + l;
+    double v[2] = {0.0, 0.0}, t[2];
+    if (j < d) {
+        const float s = bscale[j / 32];
+        for (int64_t i = w; i < n; i += kRowW) {
+            const double x = X[i * d + j];
+            const double r = (double)s * (double)quantise(x, s) - x;
+            if (r > 0) v[0] += r; else v[1] -= r;
+        }
     }
-    e[j] = fmax(pos, neg) * (1.0 + 1e-12);
+    combine_rows<2>(part, v, t);
+    if (j < d && w == 0) e[j] = fmax(t[0], t[1]) * (1.0 + 1e-12);
 }
 
 // cabs_j = sum_i |X~_ij| rounded up to float; 0 for padded columns.
-__global__ void cabs_kernel(const double* X, int64_t n, int64_t d, int64_t dpad, float* cabs) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= dpad) return;
+__global__ __launch_bounds__(kColW * kRowW) void cabs_kernel(const double* X, int64_t n, int64_t d, int64_t dpad,
+                                                              float* cabs) {
+    __shared__ double part[1][kRowW][kColW];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * kColW + l;
+    double v[1] = {0.0}, t[1];
+    if (j < d)
+        for (int64_t i = w; i < n; i += kRowW) v[0] += fabs(X[i * d + j]);
+    combine_rows<1>(part, v, t);
+    if (j >= dpad || w != 0) return;
     if (j >= d) {
         cabs[j] = 0.f;
         return;
     }
-    double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += fabs(X[i * d + j]);
-    s *= 1.0 + 1e-12;   // cover the FP64 rounding of the sum itself
+    const double s = t[0] * (1.0 + 1e-12);   // cover the FP64 rounding of the sum itself
     float f = (float)s;
     if ((double)f < s) f = nextafterf(f, INFINITY);
     cabs[j] = f;
@@ -322,39 +356,46 @@ __global__ void cabs_kernel(const double* X, int64_t n, int64_t d, int64_t dpad,
 //       set sums to more than either;
 //   [3] fp32: sum_i |x_ij| (ks - i / 16), the VALU running-total adds unit i passes through;
 //   [4] fp32: max(sum of the positive, sum of the negative) residuals x - float(x).
-__global__ void bound_sums_kernel(const double* X, int64_t n, int64_t d, int64_t ks, double* out) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= d) return;
+__global__ __launch_bounds__(kColW * kRowW) void bound_sums_kernel(const double* X, int64_t n, int64_t d, int64_t ks,
+                                                                    double* out) {
+    __shared__ double part[7][kRowW][kColW];
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * kColW + l;
     auto x = [&](int64_t i) -> double { return i < n ? X[i * d + j] : 0.0; };
-    double wsplit = 0.0, rsp = 0.0, rsn = 0.0, wf = 0.0, rfp = 0.0, rfn = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        const double v = x(i), a = fabs(v);
-        const int64_t ki = 2 * (i / 32) + ((i % 16) >= 8 ? 1 : 0);
-        wsplit += a * (double)(4 * (ks - ki));
-        wf += a * (double)(ks - i / 16);
-        // the operand records' hi / lo: exact differences in FP64
-        const double hi = (double)bf16_to_float(bf16_rne((float)v));
-        const double r1 = v - hi;
-        const double r = r1 - (double)bf16_to_float(bf16_rne((float)r1));
-        if (r > 0) rsp += r; else rsn -= r;
-        const double rf = v - (double)(float)v;
-        if (rf > 0) rfp += rf; else rfn -= rf;
-    }
-    double tsplit = 0.0;
-    for (int64_t k = 0; k < ks; ++k) {
-        const int64_t base = 32 * (k / 2) + 8 * (k % 2);
-        for (int h = 0; h < 2; ++h) {
-            double m = 0.0;
-            for (int t = 0; t < 4; ++t) m = fmax(m, fmax(fabs(x(base + 4 * h + t)), fabs(x(base + 16 + 4 * h + t))));
-            tsplit += m;
+    // wsplit, tsplit, rsp, rsn, wf, rfp, rfn
+    double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, t[7];
+    if (j < d) {
+        for (int64_t i = w; i < n; i += kRowW) {
+            const double xv = x(i), a = fabs(xv);
+            const int64_t ki = 2 * (i / 32) + ((i % 16) >= 8 ? 1 : 0);
+            v[0] += a * (double)(4 * (ks - ki));
+            v[4] += a * (double)(ks - i / 16);
+            // the operand records' hi / lo: exact differences in FP64
+            const double hi = (double)bf16_to_float(bf16_rne((float)xv));
+            const double r1 = xv - hi;
+            const double r = r1 - (double)bf16_to_float(bf16_rne((float)r1));
+            if (r > 0) v[2] += r; else v[3] -= r;
+            const double rf = xv - (double)(float)xv;
+            if (rf > 0) v[5] += rf; else v[6] -= rf;
+        }
+        for (int64_t k = w; k < ks; k += kRowW) {
+            const int64_t base = 32 * (k / 2) + 8 * (k % 2);
+            for (int h = 0; h < 2; ++h) {
+                double m = 0.0;
+                for (int q = 0; q < 4; ++q)
+                    m = fmax(m, fmax(fabs(x(base + 4 * h + q)), fabs(x(base + 16 + 4 * h + q))));
+                v[1] += m;
+            }
         }
     }
+    combine_rows<7>(part, v, t);
+    if (j >= d || w != 0) return;
     const double up = 1.0 + 1e-12;   // cover the FP64 rounding of the sums
-    out[j] = wsplit * up;
-    out[d + j] = tsplit * up;
-    out[2 * d + j] = fmax(rsp, rsn) * up;
-    out[3 * d + j] = wf * up;
-    out[4 * d + j] = fmax(rfp, rfn) * up;
+    out[j] = t[0] * up;
+    out[d + j] = t[1] * up;
+    out[2 * d + j] = fmax(t[2], t[3]) * up;
+    out[3 * d + j] = t[4] * up;
+    out[4 * d + j] = fmax(t[5], t[6]) * up;
 }
 
 static hipError_t gemm_nt(hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
@@ -435,8 +476,8 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     RR_PHIP(hipMalloc(&bad, sizeof(int)));
     RR_PHIP(hipMemsetAsync(bad, 0, sizeof(int), st));
 
-    hipLaunchKernelGGL(mean_center_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, dX, x_dtype,
-                       n, d, ldx, P.mu, P.X64);
+    hipLaunchKernelGGL(mean_center_kernel, dim3((unsigned)((d + kColW - 1) / kColW)), dim3(kColW * kRowW), 0, st, dX,
+                       x_dtype, n, d, ldx, P.mu, P.X64);
     RR_PHIP(hipGetLastError());
     // S = Xc^T Xc / (n - 1) into L's buffer, then factor in place.
     double* A = P.L;
@@ -490,18 +531,19 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     hipLaunchKernelGGL(operands_kernel, dim3((unsigned)(P.ks * P.ncb)), dim3(64), 0, st, P.X64, n, d, P.ks, P.ncb,
                        P.op_split, P.op_f32);
     RR_PHIP(hipGetLastError());
-    hipLaunchKernelGGL(cabs_kernel, dim3((unsigned)((dpad + 255) / 256)), dim3(256), 0, st, P.X64, n, d, dpad,
-                       P.cabs);
+    hipLaunchKernelGGL(cabs_kernel, dim3((unsigned)((dpad + kColW - 1) / kColW)), dim3(kColW * kRowW), 0, st, P.X64,
+                       n, d, dpad, P.cabs);
     RR_PHIP(hipGetLastError());
     hipLaunchKernelGGL(block_scale_kernel, dim3((unsigned)P.ncb), dim3(256), 0, st, P.X64, n, d, P.bscale);
     RR_PHIP(hipGetLastError());
     hipLaunchKernelGGL(operands_i8_kernel, dim3((unsigned)(P.ks * P.ncb)), dim3(64), 0, st, P.X64, n, d, P.ncb,
                        P.bscale, P.op_i8);
     RR_PHIP(hipGetLastError());
-    hipLaunchKernelGGL(qerr_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, P.X64, n, d, P.bscale, qe);
+    hipLaunchKernelGGL(qerr_kernel, dim3((unsigned)((d + kColW - 1) / kColW)), dim3(kColW * kRowW), 0, st, P.X64, n,
+                       d, P.bscale, qe);
     RR_PHIP(hipGetLastError());
-    hipLaunchKernelGGL(bound_sums_kernel, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, P.X64, n, d, P.ks,
-                       qe + d);
+    hipLaunchKernelGGL(bound_sums_kernel, dim3((unsigned)((d + kColW - 1) / kColW)), dim3(kColW * kRowW), 0, st,
+                       P.X64, n, d, P.ks, qe + d);
     RR_PHIP(hipGetLastError());
     {
         std::vector<float> hc((size_t)dpad);
@@ -585,7 +627,8 @@ rr_status ensure_gram(Problem& P, hipStream_t st) {
     if (e != hipSuccess) return fail(e);
     hipLaunchKernelGGL(operands_kernel, dim3((unsigned)(P.ks * ncb)), dim3(64), 0, st, K, n, n, P.ks, ncb, op,
                        (uint4*)nullptr);
-    hipLaunchKernelGGL(cabs_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, st, K, n, n, npad, cabs);
+    hipLaunchKernelGGL(cabs_kernel, dim3((unsigned)((npad + kColW - 1) / kColW)), dim3(kColW * kRowW), 0, st, K, n, n,
+                       npad, cabs);
     if ((e = hipGetLastError()) != hipSuccess) return fail(e);
     std::vector<float> hc((size_t)npad);
     if ((e = hipMemcpyAsync(hc.data(), cabs, sizeof(float) * npad, hipMemcpyDeviceToHost, st)) != hipSuccess ||
