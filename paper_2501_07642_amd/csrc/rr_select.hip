@@ -716,7 +716,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
     const uint32_t band_cap = 1u << 20;
     WS w;
     if ((s = ensure_ws(P, cand_cap, acc_cap, band_cap, chunk * wpd, &w)) != RR_OK) return s;
-    if ((s = ensure_streams(P, 4 * nchunks + 5, st)) != RR_OK) return s;
+    if ((s = ensure_streams(P, 4 * nchunks + 1, st)) != RR_OK) return s;
     const void* const ws_in_use = P.ws;
     const Bound b = bound_constants(P, prec);
     const uint64_t* binom = exact ? binom_table(P.device) : nullptr;
@@ -735,8 +735,11 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         RR_HIP(hipGetLastError());
     }
     hipEvent_t* ev = P.events.data();
-    hipEvent_t ev_start = ev[0], *ev_ready = ev + 1, *ev_free = ev + 3;
-    hipEvent_t* ev_t = ev + 5;   // per chunk: contract start/end, gen start/end
+    // per chunk c: contraction start / end (4c, 4c + 1), generation start / end (4c + 2, 4c + 3);
+    // the ends also order the two streams: chunk c's contraction waits for its generation, and
+    // generation into a bitmask buffer waits for the contraction of the chunk that last used it
+    hipEvent_t ev_start = ev[0];
+    hipEvent_t* ev_t = ev + 1;
     const int cus = device_cus(P.device);
     GenArgs g{};
     g.seed = seed;
@@ -756,7 +759,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         const int bsel = (int)(c & 1);
         const uint64_t off = c * chunk;
         const uint64_t num = std::min<uint64_t>(N - off, chunk);
-        if (c >= 2) RR_HIP(hipStreamWaitEvent(P.gen_stream, ev_free[bsel], 0));
+        if (c >= 2) RR_HIP(hipStreamWaitEvent(P.gen_stream, ev_t[4 * (c - 2) + 1], 0));
         g.key_begin = key_begin + off;
         g.num = num;
         g.out = w.bits[bsel];
@@ -765,8 +768,7 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         RR_HIP(launch_gen(P.S, exact, g, (int)std::min<uint64_t>((gen_units + 3) / 4, (uint64_t)cus * tn.gen_wg),
                           P.gen_stream));
         RR_HIP(hipEventRecord(ev_t[4 * c + 3], P.gen_stream));
-        RR_HIP(hipEventRecord(ev_ready[bsel], P.gen_stream));
-        RR_HIP(hipStreamWaitEvent(st, ev_ready[bsel], 0));
+        RR_HIP(hipStreamWaitEvent(st, ev_t[4 * c + 3], 0));
         a.bits = w.bits[bsel];
         a.num = num;
         a.key_begin = key_begin + off;
@@ -775,7 +777,6 @@ rr_status draw_pipeline(Problem& P, bool exact, uint64_t seed, uint64_t key_begi
         RR_HIP(hipEventRecord(ev_t[4 * c], st));
         RR_HIP(launch_contract(P.S, prec, tn.db, false, a, (int)std::min<uint64_t>(tiles, (uint64_t)cus), st));
         RR_HIP(hipEventRecord(ev_t[4 * c + 1], st));
-        RR_HIP(hipEventRecord(ev_free[bsel], st));
         if (mode == RR_MODE_QUANTILE && c + 1 < nchunks && (c == 0 || c % 8 == 7)) {
             RR_HIP(run_select(w, st));
             hipLaunchKernelGGL(update_U_kernel, dim3(1), dim3(1), 0, st, w.ctl);
