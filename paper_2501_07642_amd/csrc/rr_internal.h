@@ -63,7 +63,8 @@ struct Problem {
     int64_t ks = 0;        // K steps of 16 units, a multiple of kKStepsPerStage (units >= n are zero)
     int64_t ncb = 0;       // covariate blocks of 32 (padded)
     double scale = 0;      // n / (n1 n0)
-    // device buffers
+    // device buffers (X64 .. bscale and cabs are carved from one allocation, mem)
+    void* mem = nullptr;
     double* X64 = nullptr;     // n x d whitened, centred covariates X~ (FP64, row-major)
     double* L = nullptr;       // d x d Cholesky factor of S_lam (lower)
     double* mu = nullptr;      // d column means

@@ -442,14 +442,11 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
     P.scale = (double)n / ((double)n1 * (double)(n - n1));
     const int64_t dpad = 32 * P.ncb;
 
-    double *S = nullptr, *piv = nullptr, *scal = nullptr, *qe = nullptr;
+    double *piv = nullptr, *scal = nullptr, *qe = nullptr;
     int* bad = nullptr;
+    void* tmp = nullptr;   // qe, piv, scal and bad: one allocation for the call
     auto fail = [&](rr_status s) {
-        hipFree(qe);
-        hipFree(S);
-        hipFree(piv);
-        hipFree(scal);
-        hipFree(bad);
+        hipFree(tmp);
         rr_free(h);
         return s;
     };
@@ -461,19 +458,40 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
             return fail(RR_E_DEVICE);                                                     \
         }                                                                                 \
     } while (0)
-    RR_PHIP(hipMalloc(&P.X64, sizeof(double) * (n * d + kX64Pad)));
+    {
+        // the handle's buffers in one allocation (and the call's temporaries in another): a
+        // prepare of a small problem is otherwise dominated by allocator calls
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = off;
+            off += (bytes + 255) & ~size_t(255);
+            return o;
+        };
+        const size_t o_x = take(sizeof(double) * (n * d + kX64Pad)), o_l = take(sizeof(double) * d * d),
+                     o_mu = take(sizeof(double) * d), o_sp = take(sizeof(uint4) * kRecordU4 * P.ks * P.ncb),
+                     o_f32 = take(sizeof(uint4) * kRecordU4 * P.ks * P.ncb), o_cabs = take(sizeof(float) * dpad),
+                     o_i8 = take(sizeof(uint4) * kRecordU4I8 * P.ks * P.ncb), o_bs = take(sizeof(float) * P.ncb);
+        RR_PHIP(hipMalloc(&P.mem, off));
+        char* b = static_cast<char*>(P.mem);
+        P.X64 = reinterpret_cast<double*>(b + o_x);
+        P.L = reinterpret_cast<double*>(b + o_l);
+        P.mu = reinterpret_cast<double*>(b + o_mu);
+        P.op_split = reinterpret_cast<uint4*>(b + o_sp);
+        P.op_f32 = reinterpret_cast<uint4*>(b + o_f32);
+        P.cabs = reinterpret_cast<float*>(b + o_cabs);
+        P.op_i8 = reinterpret_cast<uint4*>(b + o_i8);
+        P.bscale = reinterpret_cast<float*>(b + o_bs);
+        off = 0;
+        const size_t o_qe = take(sizeof(double) * 6 * d),   // e_j, then the five bound sums
+            o_piv = take(sizeof(double) * d), o_scal = take(sizeof(double) * 2), o_bad = take(sizeof(int));
+        RR_PHIP(hipMalloc(&tmp, off));
+        char* t = static_cast<char*>(tmp);
+        qe = reinterpret_cast<double*>(t + o_qe);
+        piv = reinterpret_cast<double*>(t + o_piv);
+        scal = reinterpret_cast<double*>(t + o_scal);
+        bad = reinterpret_cast<int*>(t + o_bad);
+    }
     RR_PHIP(hipMemsetAsync(P.X64 + n * d, 0, sizeof(double) * kX64Pad, st));
-    RR_PHIP(hipMalloc(&P.L, sizeof(double) * d * d));
-    RR_PHIP(hipMalloc(&P.mu, sizeof(double) * d));
-    RR_PHIP(hipMalloc(&P.op_split, sizeof(uint4) * kRecordU4 * P.ks * P.ncb));
-    RR_PHIP(hipMalloc(&P.op_f32, sizeof(uint4) * kRecordU4 * P.ks * P.ncb));
-    RR_PHIP(hipMalloc(&P.cabs, sizeof(float) * dpad));
-    RR_PHIP(hipMalloc(&P.op_i8, sizeof(uint4) * kRecordU4I8 * P.ks * P.ncb));
-    RR_PHIP(hipMalloc(&P.bscale, sizeof(float) * P.ncb));
-    RR_PHIP(hipMalloc(&qe, sizeof(double) * 6 * d));   // e_j, then the five bound sums
-    RR_PHIP(hipMalloc(&piv, sizeof(double) * d));
-    RR_PHIP(hipMalloc(&scal, sizeof(double) * 2));
-    RR_PHIP(hipMalloc(&bad, sizeof(int)));
     RR_PHIP(hipMemsetAsync(bad, 0, sizeof(int), st));
 
     hipLaunchKernelGGL(mean_center_kernel, dim3((unsigned)((d + kColW - 1) / kColW)), dim3(kColW * kRowW), 0, st, dX,
@@ -583,13 +601,8 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
         std::tie(P.esplit_n2, P.esplit_max) = norm2(es);
         std::tie(P.ef32_n2, P.ef32_max) = norm2(ef);
     }
-    hipFree(qe);
-    hipFree(S);
-    hipFree(piv);
-    hipFree(scal);
-    hipFree(bad);
-    qe = S = piv = scal = nullptr;
-    bad = nullptr;
+    hipFree(tmp);
+    tmp = nullptr;
     // the device's binomial table (exact-mode keys), so that later calls find it without allocating
     if (!binom_table(device)) {
         set_error("rr_prepare: binomial table allocation failed");

@@ -968,15 +968,8 @@ void rr_free(rr_problem* p) {
     if (!p) return;
     Problem& P = p->P;
     hipDeviceSynchronize();   // asynchronous calls on this handle may still be running
-    hipFree(P.X64);
-    hipFree(P.L);
-    hipFree(P.mu);
-    hipFree(P.op_split);
-    hipFree(P.op_f32);
-    hipFree(P.op_i8);
-    hipFree(P.bscale);
+    hipFree(P.mem);   // X64, L, mu, the operand records, bscale, cabs
     hipFree(P.op_gram);
-    hipFree(P.cabs);
     park(P);   // the workspaces go to the next handle on this device
     for (hipEvent_t e : P.events) hipEventDestroy(e);
     if (P.gen_stream) hipStreamDestroy(P.gen_stream);
