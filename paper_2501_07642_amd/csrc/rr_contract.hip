@@ -226,12 +226,24 @@ void contract_kernel(ContractArgs a0) {
 #pragma unroll
                         for (int db = 0; db < DB; ++db)
                             acc[cb][db] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Acur[cb][p], Bc[db], acc[cb][db], 0, 0, 0);
-                        __builtin_amdgcn_sched_barrier(0);
                         if (more)
                             An[cb][p] = __builtin_bit_cast(bf16x8, st[(((kk + 1) * CB + cb) * 2 + p) * 64 + lane]);
                         else
                             An[cb][p] = __builtin_bit_cast(bf16x8, stn[(cb * 2 + p) * 64 + lane]);
-                        if (more && g < DB) Bn[g] = expand(kk + 1, g);
+                        if (more && g < DB) {
+                            Bn[g] = expand(kk + 1, g);
+                            // each MFMA followed by half of the expansion, then the read
+#pragma unroll
+                            for (int db = 0; db < DB; ++db) {
+                                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                                __builtin_amdgcn_sched_group_barrier(0x002, 8 / DB, 0);
+                            }
+                            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                        } else {
+                            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                            __builtin_amdgcn_sched_group_barrier(0x008, DB - 1, 0);
+                        }
                     }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
