@@ -82,6 +82,9 @@ void contract_kernel(ContractArgs a0) {
     constexpr int WSTR = 8 * S + 1;                       // +1: 32 draws hit 32 banks
     constexpr bool kGram = PREC == RR_PREC_GRAM_BF16;
     constexpr bool kSplitLike = PREC == RR_PREC_SPLIT_BF16 || kGram;
+    // the split form carries a stage's bitmask words and first B fragments from the stage before
+    // it (the Gram form's epilogue leaves no registers for them: it reads them per stage)
+    constexpr bool kCarry = PREC == RR_PREC_SPLIT_BF16;
     constexpr int PL = planes_for(PREC);
     constexpr int RECU4 = 64 * PL;                         // uint4 per operand record
     constexpr int REC = kKStage * CB * PL;                 // 1 KB plane records per stage
@@ -168,6 +171,37 @@ void contract_kernel(ContractArgs a0) {
 #pragma unroll
                 for (int p = 0; p < 2; ++p) Acur[cb][p] = __builtin_bit_cast(bf16x8, sA[(cb * 2 + p) * 64 + lane]);
         }
+        // split forms: B dwords of K step kk from bitmask words rotated right by 4 h (lane half h)
+        auto expand_w = [&](const uint32_t (&w)[DB][kKStage / 2], int kk, int db) {
+            const uint32_t x = w[db][kk >> 1];
+            uint4 r;
+            if (kk & 1) {
+                r = make_uint4(wdword_split<1, 0>(x), wdword_split<1, 1>(x), wdword_split<1, 2>(x),
+                               wdword_split<1, 3>(x));
+            } else {
+                r = make_uint4(wdword_split<0, 0>(x), wdword_split<0, 1>(x), wdword_split<0, 2>(x),
+                               wdword_split<0, 3>(x));
+            }
+            return __builtin_bit_cast(bf16x8, r);
+        };
+        auto rotated_words = [&](int ks, uint32_t (&w)[DB][kKStage / 2]) {
+#pragma unroll
+            for (int db = 0; db < DB; ++db)
+#pragma unroll
+                for (int q = 0; q < kKStage / 2; ++q) {
+                    const uint32_t x = myb[32 * db * WSTR + (kKStage / 2) * ks + q];
+                    w[db][q] = __builtin_amdgcn_alignbit(x, x, 4 * h);
+                }
+        };
+        // split form: rotated words of the stage about to run and the B fragments of its first
+        // step, carried across stages (the last step of a stage prepares the next stage's)
+        uint32_t wrc[DB][kKStage / 2];
+        bf16x8 Bcc[DB];
+        if constexpr (kCarry) {
+            rotated_words(0, wrc);
+#pragma unroll
+            for (int db = 0; db < DB; ++db) Bcc[db] = expand_w(wrc, 0, db);
+        }
         for (int gs = 0; gs < total; ++gs) {
             if (kst == 0) {
 #pragma unroll
@@ -181,34 +215,32 @@ void contract_kernel(ContractArgs a0) {
             const uint4* st = sA + (gs & 1) * STAGE_U4;
             // bitmask words of this stage: units 128 kst .. 128 kst + 127
             uint32_t wd[DB][kKStage / 2];
-#pragma unroll
-            for (int db = 0; db < DB; ++db)
-#pragma unroll
-                for (int q = 0; q < kKStage / 2; ++q) wd[db][q] = myb[32 * db * WSTR + (kKStage / 2) * kst + q];
-            if constexpr (kSplitLike) {
-                // Software pipeline: the B fragments of step kk + 1 are expanded between the
-                // MFMA groups of step kk (scheduling fences keep that order).
-                uint32_t wr[DB][kKStage / 2];
+            if constexpr (!kSplitLike) {
 #pragma unroll
                 for (int db = 0; db < DB; ++db)
 #pragma unroll
-                    for (int q = 0; q < kKStage / 2; ++q)
-                        wr[db][q] = __builtin_amdgcn_alignbit(wd[db][q], wd[db][q], 4 * h);
-                auto expand = [&](int kk, int db) {
-                    const uint32_t x = wr[db][kk >> 1];
-                    uint4 r;
-                    if (kk & 1) {
-                        r = make_uint4(wdword_split<1, 0>(x), wdword_split<1, 1>(x), wdword_split<1, 2>(x),
-                                       wdword_split<1, 3>(x));
-                    } else {
-                        r = make_uint4(wdword_split<0, 0>(x), wdword_split<0, 1>(x), wdword_split<0, 2>(x),
-                                       wdword_split<0, 3>(x));
-                    }
-                    return __builtin_bit_cast(bf16x8, r);
-                };
+                    for (int q = 0; q < kKStage / 2; ++q) wd[db][q] = myb[32 * db * WSTR + (kKStage / 2) * kst + q];
+            }
+            if constexpr (kSplitLike) {
+                // Software pipeline: the B fragments of step kk + 1 are expanded between the
+                // MFMA groups of step kk (scheduling groups place half an expansion after each
+                // MFMA); with the carry, the last step expands the next stage's first fragments
+                // from its words, read in the middle of the stage.
+                uint32_t wr[DB][kKStage / 2], wrn[DB][kKStage / 2];
                 bf16x8 Bc[DB], Bn[DB];
+                if constexpr (kCarry) {
 #pragma unroll
-                for (int db = 0; db < DB; ++db) Bc[db] = expand(0, db);
+                    for (int db = 0; db < DB; ++db) {
+                        Bc[db] = Bcc[db];
+#pragma unroll
+                        for (int q = 0; q < kKStage / 2; ++q) wr[db][q] = wrc[db][q];
+                    }
+                } else {
+                    rotated_words(kst, wr);
+#pragma unroll
+                    for (int db = 0; db < DB; ++db) Bc[db] = expand_w(wr, 0, db);
+                }
+                const int kstn = kst + 1 < nst ? kst + 1 : 0;   // the next stage's (after a tile's last: unused)
                 // The A fragments of step kk + 1 are read during step kk, one per MFMA group; those
                 // of the next stage's first step are read in the last step, after the barrier that
                 // makes that stage's buffer complete (after a tile's last stage the read is of a
@@ -217,7 +249,9 @@ void contract_kernel(ContractArgs a0) {
 #pragma unroll
                 for (int kk = 0; kk < kKStage; ++kk) {
                     const bool more = kk + 1 < kKStage;
+                    const bool expand_next = more || kCarry;
                     if (kk == kKStage - 1) early_barrier();
+                    if (kCarry && kk == 2) rotated_words(kstn, wrn);
                     bf16x8 An[CB][2];
 #pragma unroll
                     for (int g = 0; g < 2 * CB; ++g) {
@@ -230,8 +264,8 @@ void contract_kernel(ContractArgs a0) {
                             An[cb][p] = __builtin_bit_cast(bf16x8, st[(((kk + 1) * CB + cb) * 2 + p) * 64 + lane]);
                         else
                             An[cb][p] = __builtin_bit_cast(bf16x8, stn[(cb * 2 + p) * 64 + lane]);
-                        if (more && g < DB) {
-                            Bn[g] = expand(kk + 1, g);
+                        if (expand_next && g < DB) {
+                            Bn[g] = more ? expand_w(wr, kk + 1, g) : expand_w(wrn, 0, g);
                             // each MFMA followed by half of the expansion, then the read
 #pragma unroll
                             for (int db = 0; db < DB; ++db) {
@@ -250,9 +284,17 @@ void contract_kernel(ContractArgs a0) {
                     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
                         for (int p = 0; p < 2; ++p) Acur[cb][p] = An[cb][p];
-                    if (more) {
+                    if (expand_next) {
 #pragma unroll
                         for (int db = 0; db < DB; ++db) Bc[db] = Bn[db];
+                    }
+                }
+                if constexpr (kCarry) {
+#pragma unroll
+                    for (int db = 0; db < DB; ++db) {
+                        Bcc[db] = Bc[db];
+#pragma unroll
+                        for (int q = 0; q < kKStage / 2; ++q) wrc[db][q] = wrn[db][q];
                     }
                 }
             } else if constexpr (PREC == RR_PREC_FIXED_I8) {
