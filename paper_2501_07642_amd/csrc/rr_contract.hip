@@ -10,7 +10,12 @@
 // operand (32 covariates x 16 units of X~^T) comes from the precomputed operand records,
 // staged from global memory straight into LDS eight K steps at a time (double-buffered,
 // shared by the waves of the workgroup; the barrier that hands a stage over sits before its
-// last K step in the MFMA-16 forms); the B operand (16 units x 32 draws of W^T) is expanded from the tile's bitmasks in LDS.
+// last K step in the MFMA-16 forms); the B operand (16 units x 32 draws of W^T) is expanded
+// from the tile's bitmasks in LDS.  In the split and Gram forms a K step's MFMAs run on
+// registers filled during the step before: its A fragments are read from LDS and its B
+// fragments expanded there, half an expansion after each MFMA; the split form also reads a
+// stage's bitmask words during the stage before and expands its first B fragments in that
+// stage's last step, so every stage starts on MFMAs.
 // In an output block, lane l holds draw l % 32 and 16 covariates, so ||G||^2 is reduced in
 // registers and across the two lane halves; the error bounds need only ||G|| (or, for the
 // Gram form, the sum of |G'_j| over the treated units).  For the per-column criterion
