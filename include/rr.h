@@ -59,6 +59,9 @@ enum { RR_METRIC_MAHALANOBIS = 0, RR_METRIC_DIAGONAL = 1, RR_METRIC_MAX_SMD = 2 
 #define RR_MAX_N 4096
 /* Largest unit count for exact enumeration (bitmask of one 64-bit word). */
 #define RR_MAX_N_EXACT 64
+/* Largest covariate count: one LDS stage of the contraction's operand records stays within
+ * a 2^31-byte buffer range. */
+#define RR_MAX_D (1 << 22)
 
 /*
  * rr_prepare -- whitening and workspace set-up (section 2.2: covariates whitened so that
@@ -66,7 +69,7 @@ enum { RR_METRIC_MAHALANOBIS = 0, RR_METRIC_DIAGONAL = 1, RR_METRIC_MAX_SMD = 2 
  *
  *   d_X      device, n rows x d columns, row-major with leading dimension ldx >= d,
  *            FP64 (x_dtype = RR_X_FP64) or FP32 (RR_X_FP32, promoted to FP64).
- *   n1       treated-group size, 1 <= n1 <= n-1.  n <= RR_MAX_N, d >= 1.
+ *   n1       treated-group size, 1 <= n1 <= n-1.  n <= RR_MAX_N, 1 <= d <= RR_MAX_D.
  *   ridge_rel  lambda = ridge_rel * tr(S) / d is added to the diagonal of the sample
  *            covariance S (denominator n - 1) before the Cholesky factorisation; >= 0.
  *            With d >= n - 1, S is singular and ridge_rel > 0 is required.
@@ -75,7 +78,7 @@ enum { RR_METRIC_MAHALANOBIS = 0, RR_METRIC_DIAGONAL = 1, RR_METRIC_MAX_SMD = 2 
  * Cholesky factor L, the whitened centred covariates X~ = (X - 1 mu^T) L^-T, and from X~
  * the BF16 hi/lo and FP32 operand copies used by rr_draw_*.
  * Errors: RR_E_ARG, RR_E_SINGULAR (a pivot <= 0, or min L_jj^2 < 1e-10 max S_jj),
- * RR_E_UNSUPPORTED (n > RR_MAX_N), RR_E_DEVICE.
+ * RR_E_UNSUPPORTED (n > RR_MAX_N or d > RR_MAX_D), RR_E_DEVICE.
  */
 rr_status rr_prepare(const void* d_X, int x_dtype, int64_t n, int64_t d, int64_t ldx,
                      int64_t n1, double ridge_rel, void* stream, rr_problem** out);

@@ -68,6 +68,9 @@ __device__ __forceinline__ uint4 expand_i8(uint32_t x) {
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
+// word 3 of a raw buffer resource on gfx9-family parts: 32-bit data format, no swizzle
+constexpr int kBufferWord3 = 0x00020000;
+
 constexpr int planes_for(int prec) { return prec == RR_PREC_FIXED_I8 ? 1 : 2; }
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -128,14 +131,19 @@ void contract_kernel(ContractArgs a0) {
         for (int i = 0; i < NREC; ++i) {
             const int r = wv + i * NW;
             const int kk = r / (CB * PL), cb = (r / PL) % CB, p = r % PL;
-            roff[i] = (uint32_t)((kk * a.ncb + cb) * RECU4 + 64 * p + lane);
+            roff[i] = (uint32_t)(((kk * a.ncb + cb) * RECU4 + 64 * p + lane) * sizeof(uint4));
         }
+        // The copies are buffer loads into LDS over a resource based at the stage: their
+        // per-lane byte offsets stay below kKStage ncb records (the host keeps that under 2^31).
+        const uint32_t stage_bytes = (uint32_t)(((kKStage - 1) * a.ncb + CB) * RECU4 * sizeof(uint4));
         auto issue_stage = [&](int chunk, int kst, int buf) {
             const uint4* base = a.op + ((size_t)kst * kKStage * a.ncb + (size_t)chunk * CB) * RECU4;
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)stage_bytes, kBufferWord3);
 #pragma unroll
             for (int i = 0; i < NREC; ++i) {
-                const uint4* src = base + roff[i];
-                __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(sA + buf * STAGE_U4 + (wv + i * NW) * 64), 16, 0, 0);
+                const lds_ptr_t dst = (lds_ptr_t)(sA + buf * STAGE_U4 + (wv + i * NW) * 64);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 16, (int)roff[i], 0, 0, 0);
             }
         };
         if (tile0 >= a.num) continue;

@@ -421,6 +421,10 @@ rr_status prepare_impl(const void* dX, int x_dtype, int64_t n, int64_t d, int64_
         set_error("rr_prepare: n exceeds RR_MAX_N");
         return RR_E_UNSUPPORTED;
     }
+    if (d > RR_MAX_D) {
+        set_error("rr_prepare: d exceeds RR_MAX_D");
+        return RR_E_UNSUPPORTED;
+    }
     int device = 0;
     RR_HIP(hipGetDevice(&device));   // before the handle exists: nothing to release on failure
     static std::atomic<uint64_t> next_uid{1};

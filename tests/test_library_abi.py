@@ -50,3 +50,20 @@ def test_binding_loads_and_errors_without_device(lib):
     st = L.rr_prepare(None, 0, 10, 3, 3, 5, 0.0, None, ctypes.byref(h))
     assert rr._lib.STATUS[st] == "RR_E_ARG"
     assert b"invalid" in L.rr_last_error()
+
+
+def test_shape_limits_rejected_before_device_use(lib):
+    """n above RR_MAX_N and d above RR_MAX_D are refused before any device call (the pointer is
+    never dereferenced)."""
+    import paper_2501_07642_amd as rr
+    L = rr.load()
+    text = open(HEADER).read()
+    max_n = int(re.search(r"#define RR_MAX_N (\d+)", text).group(1))
+    max_d = eval(re.search(r"#define RR_MAX_D (\(1 << \d+\))", text).group(1))
+    fake = ctypes.c_void_p(256)
+    h = ctypes.c_void_p()
+    st = L.rr_prepare(fake, 0, max_n + 1, 3, 3, 5, 0.0, None, ctypes.byref(h))
+    assert rr._lib.STATUS[st] == "RR_E_UNSUPPORTED" and b"RR_MAX_N" in L.rr_last_error()
+    st = L.rr_prepare(fake, 0, 10, max_d + 1, max_d + 1, 5, 0.0, None, ctypes.byref(h))
+    assert rr._lib.STATUS[st] == "RR_E_UNSUPPORTED" and b"RR_MAX_D" in L.rr_last_error()
+    assert not h.value
