@@ -74,6 +74,14 @@ constexpr int kBufferWord3 = 0x00020000;
 constexpr int planes_for(int prec) { return prec == RR_PREC_FIXED_I8 ? 1 : 2; }
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// A pointer every lane of the wave holds (a batched tile's operand records come from a table
+// in memory, so the compiler cannot see that): in scalar registers, as a buffer resource needs.
+template <typename T>
+__device__ __forceinline__ const T* uniform_ptr(const T* p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const T*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
 
 template <int PREC, int NW, int CB, int DB, int S, bool BATCH>
 // 8-wave tiles: at most 168 registers per wave (two waves per SIMD, 336 of the 512 registers),
@@ -135,9 +143,11 @@ void contract_kernel(ContractArgs a0) {
         }
         // The copies are buffer loads into LDS over a resource based at the stage: their
         // per-lane byte offsets stay below kKStage ncb records (the host keeps that under 2^31).
-        const uint32_t stage_bytes = (uint32_t)(((kKStage - 1) * a.ncb + CB) * RECU4 * sizeof(uint4));
+        const int ncb_u = uniform_int(a.ncb);
+        const uint4* const op_u = uniform_ptr(a.op);
+        const uint32_t stage_bytes = (uint32_t)(((kKStage - 1) * ncb_u + CB) * RECU4 * sizeof(uint4));
         auto issue_stage = [&](int chunk, int kst, int buf) {
-            const uint4* base = a.op + ((size_t)kst * kKStage * a.ncb + (size_t)chunk * CB) * RECU4;
+            const uint4* base = op_u + ((size_t)kst * kKStage * ncb_u + (size_t)chunk * CB) * RECU4;
             const __amdgpu_buffer_rsrc_t rs =
                 __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)stage_bytes, kBufferWord3);
 #pragma unroll
