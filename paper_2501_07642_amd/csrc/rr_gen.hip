@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S <= 4 ? 8 
     uint64_t p = gw / per, i = gw - p * per;
     for (uint64_t idx = gw; idx < total; idx += nw) {
         const GenArgs& g = tab[p];
-        gen_mc_bits_fixed<S>(g.seed, g.key_begin + i, g.n, g.n1, slist[wave], g.out + i * (8 * S));
+        gen_mc_bits_fixed<S, true>(g.seed, g.key_begin + i, g.n, g.n1, slist[wave], g.out + i * (8 * S));
         __builtin_amdgcn_wave_barrier();
         i += nw;
         while (i >= per) {

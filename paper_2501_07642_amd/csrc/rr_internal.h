@@ -359,8 +359,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan_rows(uint32_t v) {
 //
 // C > 0 fixes the number of 256-unit chunks (ceil(n / 256)) at compile time: the per-chunk
 // validity tests fold away and only the last chunk keeps a runtime lane mask; C = 0 takes
-// it from n at run time.
-template <int S, int C = 0>
+// it from n at run time.  GOUT: out points to global memory (never LDS).
+template <int S, int C = 0, bool GOUT = false>
 __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, int n1, uint2* list,
                                             uint32_t* out) {
     static_assert(C >= 0 && C <= S, "chunk count within the bitmask layout");
@@ -586,33 +586,44 @@ __device__ __forceinline__ void gen_mc_bits(uint64_t seed, uint64_t key, int n, 
             // streaming stores: the bitmasks are read once, and should not push the contraction's
             // operand records out of L2
             typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-            __builtin_nontemporal_store(u32x4{w[0], w[1], w[2], w[3]}, reinterpret_cast<u32x4*>(out + 8 * s));
-            __builtin_nontemporal_store(u32x4{w[4], w[5], w[6], w[7]}, reinterpret_cast<u32x4*>(out + 8 * s) + 1);
+            if constexpr (GOUT) {
+                // out is known to be global memory: a store through a generic pointer (a batched
+                // pool's comes from a table) would be a flat store, which also counts against the
+                // LDS counter, so that the next draw's LDS reads would wait for it
+                typedef __attribute__((address_space(1))) u32x4* gptr_t;
+                const gptr_t o = (gptr_t)(out + 8 * s);
+                __builtin_nontemporal_store(u32x4{w[0], w[1], w[2], w[3]}, o);
+                __builtin_nontemporal_store(u32x4{w[4], w[5], w[6], w[7]}, o + 1);
+            } else {
+                // out may be LDS (the regeneration, FRT and recheck kernels pass per-wave buffers)
+                __builtin_nontemporal_store(u32x4{w[0], w[1], w[2], w[3]}, reinterpret_cast<u32x4*>(out + 8 * s));
+                __builtin_nontemporal_store(u32x4{w[4], w[5], w[6], w[7]}, reinterpret_cast<u32x4*>(out + 8 * s) + 1);
+            }
         }
     }
 }
 
 // gen_mc_bits with the chunk count of n fixed at compile time (S / 2 < chunks <= S).
-template <int S>
+template <int S, bool GOUT = false>
 __device__ __forceinline__ void gen_mc_bits_fixed(uint64_t seed, uint64_t key, int n, int n1, uint2* list,
                                                   uint32_t* out) {
     const int chunks = (n + kUnitsPerChunk - 1) / kUnitsPerChunk;
     if constexpr (S == 1) {
-        gen_mc_bits<1, 1>(seed, key, n, n1, list, out);
+        gen_mc_bits<1, 1, GOUT>(seed, key, n, n1, list, out);
     } else if constexpr (S == 2) {
-        gen_mc_bits<2, 2>(seed, key, n, n1, list, out);
+        gen_mc_bits<2, 2, GOUT>(seed, key, n, n1, list, out);
     } else if constexpr (S == 4) {
-        if (chunks == 4) gen_mc_bits<4, 4>(seed, key, n, n1, list, out);
-        else gen_mc_bits<4, 3>(seed, key, n, n1, list, out);
+        if (chunks == 4) gen_mc_bits<4, 4, GOUT>(seed, key, n, n1, list, out);
+        else gen_mc_bits<4, 3, GOUT>(seed, key, n, n1, list, out);
     } else if constexpr (S == 8) {
         switch (chunks) {
-            case 8: gen_mc_bits<8, 8>(seed, key, n, n1, list, out); break;
-            case 7: gen_mc_bits<8, 7>(seed, key, n, n1, list, out); break;
-            case 6: gen_mc_bits<8, 6>(seed, key, n, n1, list, out); break;
-            default: gen_mc_bits<8, 5>(seed, key, n, n1, list, out); break;
+            case 8: gen_mc_bits<8, 8, GOUT>(seed, key, n, n1, list, out); break;
+            case 7: gen_mc_bits<8, 7, GOUT>(seed, key, n, n1, list, out); break;
+            case 6: gen_mc_bits<8, 6, GOUT>(seed, key, n, n1, list, out); break;
+            default: gen_mc_bits<8, 5, GOUT>(seed, key, n, n1, list, out); break;
         }
     } else {
-        gen_mc_bits<S, 0>(seed, key, n, n1, list, out);
+        gen_mc_bits<S, 0, GOUT>(seed, key, n, n1, list, out);
     }
 }
 
